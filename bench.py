@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the DG Euler hot path (fused RHS + LSERK45 stage update) on
+one MI355X, in GDOF-RK-stages per second (solution nodes x RK stages / s, the
+paper's DOF count: Section V), with the roofline of the dominant kernel and
+the CPU oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--precision fp64|fp32]
+
+One bench step is one LSERK45 time step (five fused stages) over the whole
+mesh.  The timed region is one call that advances K steps, bracketed by
+device synchronisation; Q and res are resident in HBM before it starts.
+Prints ONE JSON line.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0         # MI355X HBM3E, published
+FP64_PEAK_TFS = 78.6          # MI355X FP64 vector, published
+ALG_BYTES_PER_DOF_STAGE = 160  # read Q, res; write Q, res (FP64, 5 fields)
+
+WORKLOADS = {
+    # name: (n, p, steps of the configuration, description)
+    "tgv32_p3": (32, 3, 100, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 32^3 elements, p=3, "
+                             "dt from CFL 0.3, 100 LSERK45 steps"),
+    "tgv48_p4": (48, 4, 50, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 48^3 elements, p=4 "
+                            "(one GPU's share at the paper's per-GPU size), 50 LSERK45 steps"),
+    "tgv40_p6": (40, 6, 100, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 40^3 elements, p=6 "
+                             "(the paper's degree), 100 LSERK45 steps"),
+}
+
+
+def flops_per_dof_stage(N):
+    """Algorithmic flops per node and stage: volume 38 + 30 N (the flop
+    model of the paper's volume kernel), surface 3 (40 N + 76) / N (trace
+    interpolation, local Lax-Friedrichs flux and lift per face point), inverse
+    mass and RK update 30."""
+    return 38 + 30 * N + 3 * (40 * N + 76) / N + 30
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kern_fp64.hip", "dg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2006_15698_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the stage kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(f"{workload}:{precision}")
+    if not ent or ent.get("kernel_src") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(n, p, L, budget_s):
+    """The oracle (plain dense FP64 numpy) advancing RK stages of the same
+    workload on the host for about ``budget_s`` seconds."""
+    import numpy as np
+    import workloads as W
+    from oracle import lserk
+    from oracle.dg import DG
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    ora = DG((n, n, n), p, L=L)
+    Q = W.tgv(n, p)
+    res = np.zeros_like(Q)
+    dt = ora.dt_cfl(Q, 0.3)
+    t0 = time.perf_counter()
+    stages = 0
+    while True:
+        lserk.stage(stages % 5, Q, res, dt, ora.rhs)
+        stages += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    dof = ora.num_dof()
+    return {"value": dof * stages / el / 1e9, "unit": "GDOF-RK-stages/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{stages} RK stages of the same workload ({dof} nodes) in {el:.1f} s; "
+                      f"BLAS threads {threads}, host cpu_count {os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="tgv32_p3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}): this build "
+              "measures one GPU's share of the mesh; the multi-GPU face exchange is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2006_15698_amd import dg
+
+    n, p, cfg_steps, desc = WORKLOADS[args.workload]
+    K = cfg_steps if args.steps is None else args.steps
+    Wm = args.warmup
+    L = (2 * math.pi,) * 3
+    prec = dg.DG_FP64 if args.precision == "fp64" else dg.DG_FP32_MFMA
+    s = dg.Solver((n, n, n), p, L=L, precision=prec)
+    dof = s.num_dof
+    Q0 = torch.from_numpy(W.tgv(n, p)).cuda()
+    dt = s.dt_cfl(Q0, 0.3)
+    Q = Q0.clone()
+    res = torch.zeros_like(Q)
+    if Wm > 0:
+        s.step(Q, res, dt, nsteps=Wm)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    s.step(Q, res, dt, nsteps=K)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    value = dof * 5 * K / (ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "GDOF-RK-stages/sec",
+        "value": value,
+        "unit": "GDOF-RK-stages/sec",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 contractions, f64 state",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "elements": n ** 3, "p": p,
+                   "dof": dof, "precision": args.precision, "dt": dt},
+    }
+
+    if not args.no_roofline:
+        # Dominant kernel: the fused stage kernel.  Average launch duration
+        # from HIP events that the library records around every launch on the
+        # stream it launches on (a second pass over the same K steps).
+        dg.dg_set_timing(s.ctx, True)
+        s.step(Q, res, dt, nsteps=K)
+        t = dg.dg_timing_read(s.ctx)
+        dg.dg_set_timing(s.ctx, False)
+        st_ms, st_n = t["stage"]
+        avg_s = st_ms / st_n * 1e-3
+        alg_bytes = ALG_BYTES_PER_DOF_STAGE * dof
+        achieved = alg_bytes / avg_s / 1e9
+        traffic = measured_traffic(args.workload, args.precision)
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel": "k_stage (fused RHS + LSERK45 stage)",
+                           "avg_launch_us": avg_s * 1e6, "launches": st_n,
+                           "alg_bytes_per_launch": alg_bytes}
+        fl = flops_per_dof_stage(p + 1) * dof
+        out["fp64_rate"] = {"achieved_tflops": fl / avg_s / 1e12, "peak_tflops": FP64_PEAK_TFS,
+                            "frac": fl / avg_s / 1e12 / FP64_PEAK_TFS,
+                            "flops_per_dof_stage": flops_per_dof_stage(p + 1)}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, p, L, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

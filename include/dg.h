@@ -1,0 +1,170 @@
+/*
+ * dg.h -- C ABI of the MI355X (gfx950) nodal discontinuous Galerkin solver
+ * core for the 3-D compressible Euler equations on a periodic Cartesian
+ * hexahedral mesh, with its five-stage fourth-order low-storage Runge-Kutta
+ * stage update.
+ *
+ * Method: Kirby & Mavriplis, "GPU-Accelerated Discontinuous Galerkin Methods:
+ * 30x Speedup on 345 Billion Unknowns".
+ *   - Equations: Eq. (1) conservation form, Eq. (2) state Q and flux columns
+ *     F^1..F^3 (total enthalpy H = E + p/rho), Eq. (3) ideal-gas closure.
+ *   - Discretisation: Section II-B, Eq. (4)-(5) weak form, Eq. (6)-(7) nodal
+ *     Lagrange basis through N = p+1 Gauss-Legendre points per direction,
+ *     collocated quadrature (Section I), Lax-Friedrichs face flux.
+ *   - Time integration: Sections II-B, IV, V: five-stage fourth-order
+ *     low-storage explicit Runge-Kutta (LSERK45).
+ *   - Volume term sum-factorised along 1-D lines: Section IV, Listing 1.
+ *
+ * Conventions that hold for every entry point:
+ *   Layout.  Every state-sized array is a DEVICE pointer to
+ *     5 * E * N^3 doubles, E = nx*ny*nz, in the order
+ *     [field][ez][ey][ex][k][j][i]: fields rho, rho u, rho v, rho w, rho E;
+ *     element index ex fastest among elements; node index i (x direction)
+ *     fastest inside an element.  Element (ex,ey,ez) covers
+ *     [ex hx,(ex+1)hx] x [ey hy,(ey+1)hy] x [ez hz,(ez+1)hz], h_d = L_d/n_d;
+ *     node (i,j,k) sits at the Gauss-Legendre points (xi_i, xi_j, xi_k) of
+ *     that box.  Neighbours are periodic.
+ *   Ownership.  The caller owns every array and the workspace (allocated by
+ *     PyTorch or hipMalloc); the library owns only the context.  The library
+ *     performs no device allocation.
+ *   Streams.  Every call runs asynchronously on the context's stream (default
+ *     stream 0 until dg_set_stream) except those marked SYNCHRONISING, which
+ *     wait for their own result.  A context is not thread-safe.
+ *   Errors.  Functions return DG_OK (0) or a negative DG_E* code and set a
+ *     thread-local message readable with dg_last_error().  Argument errors are
+ *     detected before any launch and leave every array untouched.  A failed
+ *     launch returns DG_EHIP.  Faults inside kernels surface at the next
+ *     synchronising call.  The hot path does no physical checks: a
+ *     non-physical state propagates NaN/Inf.
+ *   Aliasing.  Q must not overlap R, res or gQ (DG_EALIAS).
+ *   Degrees.  p = 0..7 (N = 1..8).
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,        /* bad argument (NULL, size, range) */
+  DG_EUNSUPPORTED = -2,  /* valid request outside what this build supports */
+  DG_EHIP = -3,          /* HIP runtime error (launch, copy, sync) */
+  DG_EALIAS = -4,        /* forbidden overlap between arrays */
+  DG_ENONPHYSICAL = -5,  /* dg_check_state found rho<=0, p<=0 or NaN/Inf */
+  DG_EWORKSPACE = -6     /* no workspace set, or too small */
+};
+
+enum {
+  DG_FP64 = 0,       /* all arithmetic in FP64 */
+  DG_FP32_MFMA = 1   /* tensor-product contractions on FP32 matrix cores,
+                        RK accumulation and all state in FP64 */
+};
+
+/* Create a context for an nx*ny*nz periodic mesh of degree p (0..7) and
+ * ratio of specific heats gamma (> 1; Eq. (3) uses 1.4).  The domain is
+ * [0,1]^3 until dg_set_domain.  Returns NULL on error (dg_last_error()).
+ * Builds the Gauss-Legendre rule, the 1-D differentiation matrix and the
+ * face interpolation weights on the host (Section II-B, Eqs. (6)-(7)). */
+dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma);
+
+/* Destroy a context (NULL is allowed).  Does not free caller memory. */
+void dg_destroy(dg_ctx* ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* dg_last_error(void);
+
+/* Domain lengths Lx, Ly, Lz (> 0); element sizes h_d = L_d / n_d. */
+int dg_set_domain(dg_ctx* ctx, double Lx, double Ly, double Lz);
+
+/* HIP stream (hipStream_t passed as void*; NULL = default stream) on which
+ * every later call of this context is enqueued. */
+int dg_set_stream(dg_ctx* ctx, void* hip_stream);
+
+/* Arithmetic of the RHS contractions: DG_FP64 (default) or DG_FP32_MFMA.
+ * DG_EUNSUPPORTED if the mode is not available for this p. */
+int dg_set_precision(dg_ctx* ctx, int mode);
+
+/* Bytes of device workspace that the compute calls need (face-trace
+ * ping-pong buffers and reduction partials).  Depends on the mesh and p. */
+size_t dg_workspace_bytes(const dg_ctx* ctx);
+
+/* Hand the context a caller-owned device workspace of at least
+ * dg_workspace_bytes() bytes, 256-byte aligned.  The caller keeps it alive
+ * until the context is destroyed or another workspace is set.
+ * DG_EWORKSPACE if too small, DG_EINVAL if NULL or misaligned. */
+int dg_set_workspace(dg_ctx* ctx, void* dptr, size_t bytes);
+
+/* Number of solution nodes E*N^3 (the paper's DOF count, Section V);
+ * every state array holds 5 times this many doubles.  -1 on NULL ctx. */
+int64_t dg_num_dof(const dg_ctx* ctx);
+
+/* Host helper: the N = p+1 point Gauss-Legendre nodes (ascending) and
+ * weights on [-1,1] used by the library (Section II-B).  xi and w are HOST
+ * arrays of N doubles. */
+int dg_quadrature(int p, double* xi, double* w);
+
+/* R = dQ/dt, the right-hand side of Eq. (5) solved for the time derivative:
+ * R = M^{-1} (volume term - surface term) per element, with the local
+ * Lax-Friedrichs flux lambda = max(|u_n-|+c-, |u_n+|+c+) at every face point.
+ * Q (read) and R (written) are device arrays in the layout above. */
+int dg_rhs(dg_ctx* ctx, const double* Q, double* R);
+
+/* One LSERK45 stage s (0..4) in place (Sections IV-V):
+ *   res <- a_s res + dt R(Q)   (s = 0 overwrites res: a_0 = 0)
+ *   Q   <- Q + b_s res
+ * with the Carpenter-Kennedy (5,4) 2N-storage coefficients.  Q and res are
+ * device arrays in the layout above; res is read only for s > 0. */
+int dg_rk_stage(dg_ctx* ctx, int s, double* Q, double* res, double dt);
+
+/* One LSERK45 time step (five stages) in place. */
+int dg_rk_step(dg_ctx* ctx, double* Q, double* res, double dt);
+
+/* nsteps >= 0 LSERK45 time steps in place (the paper's benchmark advances a
+ * fixed number of steps, Section V).  Bit-identical to nsteps calls of
+ * dg_rk_step. */
+int dg_rk_steps(dg_ctx* ctx, double* Q, double* res, double dt, int nsteps);
+
+/* Vector-Jacobian product of the right-hand side: gQ = (dR/dQ)^T gR at Q,
+ * FP64, overwriting gQ.  At the kinks of max and |.| in the face flux the
+ * branch taken by the forward evaluation is differentiated (ties: the -
+ * side's wave speed; |x| has derivative +1 at x >= 0).  Q, gR (read) and gQ
+ * (written) are device arrays in the layout above; gQ must not alias Q or gR. */
+int dg_rhs_vjp(dg_ctx* ctx, const double* Q, const double* gR, double* gQ);
+
+/* SYNCHRONISING.  Domain integrals by the nodal Gauss-Legendre rule:
+ * out[0..4] = integral of the five conserved fields, out[5] = integral of
+ * the kinetic energy |rho u|^2/(2 rho).  out is a HOST array of 6 doubles.
+ * Summation order is fixed (bitwise reproducible). */
+int dg_integrals(dg_ctx* ctx, const double* Q, double out[6]);
+
+/* SYNCHRONISING.  *out = max over nodes of sum_d (|u_d| + c)/h_d
+ * (units 1/time; a CFL time step is CFL/((2p+1) * *out)).  out is HOST. */
+int dg_max_wavespeed(dg_ctx* ctx, const double* Q, double* out);
+
+/* SYNCHRONISING.  DG_OK if every node has finite values, rho > 0 and
+ * p > 0; DG_ENONPHYSICAL otherwise. */
+int dg_check_state(dg_ctx* ctx, const double* Q);
+
+/* Opt-in per-launch timing for benchmarks.  While on, the context brackets
+ * every kernel it launches with HIP events on its stream (a few microseconds
+ * of overhead per launch).  Kinds: 0 face-trace kernel, 1 RK stage kernel,
+ * 2 RHS kernel, 3 adjoint kernels, 4 reductions.  Switching on clears the
+ * record; at most 65536 launches are recorded. */
+int dg_set_timing(dg_ctx* ctx, int on);
+
+/* SYNCHRONISING.  Summed milliseconds ms[k] and launch counts count[k] for
+ * the five kinds above since timing was switched on.  HOST arrays of 5. */
+int dg_timing_read(dg_ctx* ctx, double ms[5], int64_t count[5]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

@@ -1,0 +1,488 @@
+// Host side of the C ABI declared in include/dg.h: argument validation,
+// constant tables, workspace carve-up and kernel sequencing.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(int err, const char* what) {
+  return fail(DG_EHIP, "%s: HIP error %d (%s)", what, err, hipGetErrorString((hipError_t)err));
+}
+
+// Per-launch HIP-event timing (dg_set_timing).
+enum { TK_TRACE = 0, TK_STAGE = 1, TK_RHS = 2, TK_VJP = 3, TK_RED = 4, TK_NKIND = 5 };
+constexpr size_t kMaxTimed = 65536;
+
+struct DGTiming {
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  std::vector<int> kind;
+  size_t used = 0;
+  ~DGTiming() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+// Run `launch` (returning a hipError_t as int), bracketed by events when
+// timing is on.
+template <class F>
+int timed(dg_ctx* c, int kind, F&& launch) {
+  if (!c->timing_on) return launch();
+  DGTiming* T = (DGTiming*)c->timing;
+  if (T->used >= kMaxTimed) return launch();
+  if (T->ev.size() < 2 * (T->used + 1)) {
+    hipEvent_t a, b;
+    int err = (int)hipEventCreate(&a);
+    if (err) return err;
+    err = (int)hipEventCreate(&b);
+    if (err) return err;
+    T->ev.push_back(a);
+    T->ev.push_back(b);
+  }
+  hipEvent_t a = T->ev[2 * T->used], b = T->ev[2 * T->used + 1];
+  int err = (int)hipEventRecord(a, c->stream);
+  if (err) return err;
+  err = launch();
+  if (err) return err;
+  err = (int)hipEventRecord(b, c->stream);
+  if (err) return err;
+  if (T->kind.size() <= T->used) T->kind.push_back(kind);
+  else T->kind[T->used] = kind;
+  T->used++;
+  return 0;
+}
+
+// Carpenter-Kennedy (5,4) 2N-storage coefficients: the five-stage fourth-order
+// low-storage scheme named in Sections IV-V (coefficients not printed in the
+// paper; the standard published values).
+const double kRKA[5] = {0.0,
+                        -567301805773.0 / 1357537059087.0,
+                        -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0,
+                        -1275806237668.0 / 842570457699.0};
+const double kRKB[5] = {1432997174477.0 / 9575080441755.0,
+                        5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0,
+                        3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+// Legendre P_n(x) and P_n'(x) by the three-term recurrence.
+void legendre(int n, double x, double* pn, double* dpn) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    *pn = 1.0;
+    *dpn = 0.0;
+    return;
+  }
+  for (int k = 2; k <= n; ++k) {
+    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *pn = p1;
+  *dpn = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+// N-point Gauss-Legendre rule (Section II-B): Newton iteration on P_N from
+// Chebyshev-like initial guesses, weights 2 / ((1 - x^2) P_N'(x)^2).
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double pn, dpn;
+      legendre(n, z, &pn, &dpn);
+      const double dz = pn / dpn;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    double pn, dpn;
+    legendre(n, z, &pn, &dpn);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dpn * dpn);
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;  // exact centre node for odd n
+  // enforce the symmetry of the rule
+  for (int i = 0; i < n / 2; ++i) {
+    const double xs = 0.5 * (x[n - 1 - i] - x[i]);
+    const double ws = 0.5 * (w[n - 1 - i] + w[i]);
+    x[i] = -xs;
+    x[n - 1 - i] = xs;
+    w[i] = ws;
+    w[n - 1 - i] = ws;
+  }
+}
+
+void build_tables(dg_ctx* c) {
+  const int N = c->N;
+  DGTables& t = c->tab;
+  std::memset(&t, 0, sizeof(t));
+  gauss_legendre(N, c->xi, c->w);
+  // barycentric weights 1 / prod_{m != i} (xi_i - xi_m)
+  double bw[DG_MAXN];
+  for (int i = 0; i < N; ++i) {
+    double prod = 1.0;
+    for (int m = 0; m < N; ++m)
+      if (m != i) prod *= (c->xi[i] - c->xi[m]);
+    bw[i] = 1.0 / prod;
+  }
+  // D[a][i] = l_i'(xi_a): off-diagonal (bw_i / bw_a) / (xi_a - xi_i),
+  // diagonal from the zero row sum (derivative of a constant).
+  double D[DG_MAXN][DG_MAXN];
+  for (int a = 0; a < N; ++a) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) {
+      if (i == a) continue;
+      D[a][i] = (bw[i] / bw[a]) / (c->xi[a] - c->xi[i]);
+      s += D[a][i];
+    }
+    D[a][a] = -s;
+  }
+  for (int i = 0; i < N; ++i) {
+    double lm = 1.0, lp = 1.0;
+    for (int m = 0; m < N; ++m) {
+      if (m == i) continue;
+      lm *= (-1.0 - c->xi[m]) / (c->xi[i] - c->xi[m]);
+      lp *= (1.0 - c->xi[m]) / (c->xi[i] - c->xi[m]);
+    }
+    t.lm[i] = lm;
+    t.lp[i] = lp;
+    t.liftm[i] = lm / c->w[i];
+    t.liftp[i] = lp / c->w[i];
+    t.w[i] = c->w[i];
+    for (int a = 0; a < N; ++a) t.Dh[i * N + a] = c->w[a] * D[a][i] / c->w[i];
+  }
+  const double h[3] = {c->L[0] / c->nx, c->L[1] / c->ny, c->L[2] / c->nz};
+  for (int d = 0; d < 3; ++d) {
+    t.sc[d] = 2.0 / h[d];
+    t.hinv[d] = 1.0 / h[d];
+  }
+  t.J = h[0] * h[1] * h[2] / 8.0;
+  t.gamma = c->gamma;
+  t.gm1 = c->gamma - 1.0;
+  t.nx = c->nx;
+  t.ny = c->ny;
+  t.nz = c->nz;
+  t.E = (int)c->E;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + bytes && pb < pa + bytes;
+}
+
+int check_ready(dg_ctx* c) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  const DGWorkspace L = dg_workspace_layout(c);
+  if (!c->ws) return fail(DG_EWORKSPACE, "no workspace set (need %zu bytes)", L.total);
+  if (c->ws_bytes < L.total) return fail(DG_EWORKSPACE, "workspace %zu bytes < %zu", c->ws_bytes, L.total);
+  return DG_OK;
+}
+
+size_t state_bytes(const dg_ctx* c) { return (size_t)c->E * c->N * c->N * c->N * DG_NF * sizeof(double); }
+
+double* trace_buf(dg_ctx* c, int which) {
+  const DGWorkspace L = dg_workspace_layout(c);
+  return (double*)(c->ws + (which ? L.off_trace1 : L.off_trace0));
+}
+
+int run_reduce(dg_ctx* c, const double* Q, double out[DG_RED_VALS]) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!Q) return fail(DG_EINVAL, "NULL state");
+  const DGWorkspace L = dg_workspace_layout(c);
+  double* red = (double*)(c->ws + L.off_red);
+  int err = timed(c, TK_RED, [&] { return dg_launch_reduce(c, Q, red); });
+  if (err) return hip_fail(err, "reduce launch");
+  err = (int)hipMemcpyAsync(out, red + DG_RED_BLOCKS * DG_RED_VALS, DG_RED_VALS * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream);
+  if (err) return hip_fail(err, "reduce copy");
+  err = (int)hipStreamSynchronize(c->stream);
+  if (err) return hip_fail(err, "reduce sync");
+  return DG_OK;
+}
+
+int stages(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
+  // Traces of the initial Q, then `count` stages starting at stage s0; each
+  // stage but the last writes the traces of its updated Q for the next.
+  int err = timed(c, TK_TRACE, [&] { return dg_launch_trace(c, Q, trace_buf(c, 0)); });
+  if (err) return hip_fail(err, "trace launch");
+  const bool f32 = c->precision == DG_FP32_MFMA;
+  for (int g = 0; g < count; ++g) {
+    const int s = (s0 + g) % 5;
+    const double* tin = trace_buf(c, g & 1);
+    double* tout = g + 1 < count ? trace_buf(c, (g + 1) & 1) : nullptr;
+    err = timed(c, TK_STAGE, [&] {
+      return f32 ? dg_launch_stage_f32(c, Q, res, tin, tout, kRKA[s], kRKB[s], dt, s == 0)
+                 : dg_launch_stage(c, Q, res, tin, tout, kRKA[s], kRKB[s], dt, s == 0);
+    });
+    if (err) return hip_fail(err, "stage launch");
+  }
+  return DG_OK;
+}
+
+int check_state_pair(dg_ctx* c, const void* a, const char* an, const void* b, const char* bn) {
+  if (!a || !b) return fail(DG_EINVAL, "NULL %s", !a ? an : bn);
+  if (overlap(a, b, state_bytes(c))) return fail(DG_EALIAS, "%s overlaps %s", an, bn);
+  return DG_OK;
+}
+
+}  // namespace
+
+DGWorkspace dg_workspace_layout(const dg_ctx* c) {
+  DGWorkspace L;
+  const size_t N2 = (size_t)c->N * c->N;
+  const size_t N3 = N2 * c->N;
+  L.trace_bytes = align256(30 * N2 * (size_t)c->E * sizeof(double));
+  L.off_trace0 = 0;
+  L.off_trace1 = L.off_trace0 + L.trace_bytes;
+  L.off_red = L.off_trace1 + L.trace_bytes;
+  const size_t red_bytes = align256((DG_RED_BLOCKS + 1) * DG_RED_VALS * sizeof(double));
+  L.off_vjp = L.off_red + red_bytes;
+  // adjoint scratch: face-flux adjoints (30 N^2 E) and the lifted trace
+  // adjoints of both sides (2 * 30 N^2 E), plus the state-sized volume part
+  const size_t vjp_bytes = align256(3 * 30 * N2 * (size_t)c->E * sizeof(double)) +
+                           align256(DG_NF * N3 * (size_t)c->E * sizeof(double));
+  L.total = L.off_vjp + vjp_bytes;
+  return L;
+}
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_err; }
+
+dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
+  if (nx < 1 || ny < 1 || nz < 1) {
+    fail(DG_EINVAL, "mesh sizes must be >= 1 (got %d x %d x %d)", nx, ny, nz);
+    return nullptr;
+  }
+  if (p < 0 || p >= DG_MAXN) {
+    fail(DG_EUNSUPPORTED, "p must be in 0..%d (got %d)", DG_MAXN - 1, p);
+    return nullptr;
+  }
+  if (!(gamma > 1.0) || !std::isfinite(gamma)) {
+    fail(DG_EINVAL, "gamma must be finite and > 1 (got %g)", gamma);
+    return nullptr;
+  }
+  const int64_t E = (int64_t)nx * ny * nz;
+  if (E > 0x7fffffffLL) {
+    fail(DG_EUNSUPPORTED, "element count %lld exceeds 2^31-1", (long long)E);
+    return nullptr;
+  }
+  dg_ctx* c = new (std::nothrow) dg_ctx;
+  if (!c) {
+    fail(DG_EINVAL, "out of host memory");
+    return nullptr;
+  }
+  std::memset(c, 0, sizeof(*c));
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->p = p;
+  c->N = p + 1;
+  c->E = E;
+  c->gamma = gamma;
+  c->L[0] = c->L[1] = c->L[2] = 1.0;
+  c->stream = nullptr;
+  c->precision = DG_FP64;
+  build_tables(c);
+  g_err[0] = 0;
+  return c;
+}
+
+void dg_destroy(dg_ctx* c) {
+  if (!c) return;
+  delete (DGTiming*)c->timing;
+  delete c;
+}
+
+int dg_set_timing(dg_ctx* c, int on) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (on) {
+    if (!c->timing) c->timing = new (std::nothrow) DGTiming;
+    if (!c->timing) return fail(DG_EINVAL, "out of host memory");
+    ((DGTiming*)c->timing)->used = 0;
+  }
+  c->timing_on = on ? 1 : 0;
+  return DG_OK;
+}
+
+int dg_timing_read(dg_ctx* c, double ms[5], int64_t count[5]) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (!ms || !count) return fail(DG_EINVAL, "NULL output");
+  for (int k = 0; k < TK_NKIND; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  DGTiming* T = (DGTiming*)c->timing;
+  if (!T || T->used == 0) return DG_OK;
+  int err = (int)hipEventSynchronize(T->ev[2 * T->used - 1]);
+  if (err) return hip_fail(err, "timing sync");
+  for (size_t u = 0; u < T->used; ++u) {
+    float t = 0.f;
+    err = (int)hipEventElapsedTime(&t, T->ev[2 * u], T->ev[2 * u + 1]);
+    if (err) return hip_fail(err, "timing read");
+    ms[T->kind[u]] += t;
+    count[T->kind[u]] += 1;
+  }
+  return DG_OK;
+}
+
+int dg_set_domain(dg_ctx* c, double Lx, double Ly, double Lz) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (!(Lx > 0) || !(Ly > 0) || !(Lz > 0) || !std::isfinite(Lx) || !std::isfinite(Ly) || !std::isfinite(Lz))
+    return fail(DG_EINVAL, "domain lengths must be finite and > 0");
+  c->L[0] = Lx;
+  c->L[1] = Ly;
+  c->L[2] = Lz;
+  build_tables(c);
+  return DG_OK;
+}
+
+int dg_set_stream(dg_ctx* c, void* s) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  c->stream = (hipStream_t)s;
+  return DG_OK;
+}
+
+int dg_set_precision(dg_ctx* c, int mode) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (mode == DG_FP64) {
+    c->precision = mode;
+    return DG_OK;
+  }
+  if (mode == DG_FP32_MFMA) {
+    if (!dg_f32_supported(c->N)) return fail(DG_EUNSUPPORTED, "FP32 matrix-core form not built for p=%d", c->p);
+    c->precision = mode;
+    return DG_OK;
+  }
+  return fail(DG_EINVAL, "unknown precision mode %d", mode);
+}
+
+size_t dg_workspace_bytes(const dg_ctx* c) {
+  if (!c) return 0;
+  return dg_workspace_layout(c).total;
+}
+
+int dg_set_workspace(dg_ctx* c, void* dptr, size_t bytes) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (!dptr) return fail(DG_EINVAL, "NULL workspace");
+  if (((uintptr_t)dptr) & 255) return fail(DG_EINVAL, "workspace not 256-byte aligned");
+  const size_t need = dg_workspace_layout(c).total;
+  if (bytes < need) return fail(DG_EWORKSPACE, "workspace %zu bytes < %zu", bytes, need);
+  c->ws = (char*)dptr;
+  c->ws_bytes = bytes;
+  return DG_OK;
+}
+
+int64_t dg_num_dof(const dg_ctx* c) {
+  if (!c) return -1;
+  return c->E * c->N * c->N * c->N;
+}
+
+int dg_quadrature(int p, double* xi, double* w) {
+  if (p < 0 || p >= DG_MAXN) return fail(DG_EUNSUPPORTED, "p must be in 0..%d", DG_MAXN - 1);
+  if (!xi || !w) return fail(DG_EINVAL, "NULL output");
+  gauss_legendre(p + 1, xi, w);
+  return DG_OK;
+}
+
+int dg_rhs(dg_ctx* c, const double* Q, double* R) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  rc = check_state_pair(c, Q, "Q", R, "R");
+  if (rc) return rc;
+  int err = timed(c, TK_TRACE, [&] { return dg_launch_trace(c, Q, trace_buf(c, 0)); });
+  if (err) return hip_fail(err, "trace launch");
+  err = timed(c, TK_RHS, [&] {
+    return c->precision == DG_FP32_MFMA ? dg_launch_rhs_f32(c, Q, trace_buf(c, 0), R)
+                                        : dg_launch_rhs(c, Q, trace_buf(c, 0), R);
+  });
+  if (err) return hip_fail(err, "rhs launch");
+  return DG_OK;
+}
+
+int dg_rk_stage(dg_ctx* c, int s, double* Q, double* res, double dt) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (s < 0 || s > 4) return fail(DG_EINVAL, "stage must be 0..4 (got %d)", s);
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  rc = check_state_pair(c, Q, "Q", res, "res");
+  if (rc) return rc;
+  return stages(c, Q, res, dt, s, 1);
+}
+
+int dg_rk_steps(dg_ctx* c, double* Q, double* res, double dt, int nsteps) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  rc = check_state_pair(c, Q, "Q", res, "res");
+  if (rc) return rc;
+  if (nsteps == 0) return DG_OK;
+  if ((int64_t)nsteps * 5 > 0x7fffffffLL) return fail(DG_EINVAL, "too many steps");
+  return stages(c, Q, res, dt, 0, 5 * nsteps);
+}
+
+int dg_rk_step(dg_ctx* c, double* Q, double* res, double dt) { return dg_rk_steps(c, Q, res, dt, 1); }
+
+int dg_rhs_vjp(dg_ctx* c, const double* Q, const double* gR, double* gQ) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!Q || !gR || !gQ) return fail(DG_EINVAL, "NULL array");
+  if (overlap(Q, gQ, state_bytes(c))) return fail(DG_EALIAS, "gQ overlaps Q");
+  if (overlap(gR, gQ, state_bytes(c))) return fail(DG_EALIAS, "gQ overlaps gR");
+  const DGWorkspace L = dg_workspace_layout(c);
+  int err = timed(c, TK_VJP, [&] { return dg_launch_vjp(c, Q, gR, gQ, c->ws); });
+  (void)L;
+  if (err) return hip_fail(err, "vjp launch");
+  return DG_OK;
+}
+
+int dg_integrals(dg_ctx* c, const double* Q, double out[6]) {
+  if (!out) return fail(DG_EINVAL, "NULL output");
+  double v[DG_RED_VALS];
+  int rc = run_reduce(c, Q, v);
+  if (rc) return rc;
+  for (int i = 0; i < 6; ++i) out[i] = v[i];
+  return DG_OK;
+}
+
+int dg_max_wavespeed(dg_ctx* c, const double* Q, double* out) {
+  if (!out) return fail(DG_EINVAL, "NULL output");
+  double v[DG_RED_VALS];
+  int rc = run_reduce(c, Q, v);
+  if (rc) return rc;
+  *out = v[6];
+  return DG_OK;
+}
+
+int dg_check_state(dg_ctx* c, const double* Q) {
+  double v[DG_RED_VALS];
+  int rc = run_reduce(c, Q, v);
+  if (rc) return rc;
+  if (v[7] > 0) return fail(DG_ENONPHYSICAL, "%.0f node(s) with rho<=0, p<=0 or non-finite values", v[7]);
+  return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dg.h"
+
+#define DG_MAXN 8
+#define DG_NF 5
+
+// Per-context constant tables, passed by value as a kernel argument.
+// Section II-B: collocated Gauss-Legendre nodal basis (Eqs. (6)-(7)).
+struct DGTables {
+  double Dh[DG_MAXN * DG_MAXN];  // Dh[i*N+a] = w_a l_i'(xi_a) / w_i: the
+                                 // volume term of Eq. (5) on one 1-D line,
+                                 // mass matrix already divided out
+  double lm[DG_MAXN];            // l_i(-1): face interpolation weights
+  double lp[DG_MAXN];            // l_i(+1)
+  double liftm[DG_MAXN];         // l_i(-1) / w_i: surface term of Eq. (5)
+  double liftp[DG_MAXN];         // l_i(+1) / w_i   lifted by M^{-1}
+  double w[DG_MAXN];             // Gauss-Legendre weights
+  double sc[3];                  // 2 / h_d (reference-to-physical metric)
+  double hinv[3];                // 1 / h_d
+  double J;                      // h_x h_y h_z / 8 (volume Jacobian)
+  double gamma;                  // ratio of specific heats, Eq. (3)
+  double gm1;                    // gamma - 1
+  int nx, ny, nz;
+  int E;                         // nx*ny*nz
+};
+
+struct dg_ctx {
+  int nx, ny, nz, p, N;
+  int64_t E;
+  double gamma;
+  double L[3];
+  double xi[DG_MAXN], w[DG_MAXN];
+  hipStream_t stream;
+  int precision;
+  char* ws;
+  size_t ws_bytes;
+  DGTables tab;
+  int timing_on;
+  void* timing;   // DGTiming*, owned, created by dg_set_timing
+};
+
+// Workspace carve-up (byte offsets, each 256-aligned).
+struct DGWorkspace {
+  size_t trace_bytes;   // one face-trace buffer: 30 * N^2 * E doubles
+  size_t off_trace0, off_trace1;
+  size_t off_red;       // reduction partials
+  size_t off_vjp;       // adjoint scratch
+  size_t total;
+};
+DGWorkspace dg_workspace_layout(const dg_ctx* c);
+
+// Number of blocks used by the reduction kernels (fixed: the summation
+// order, and hence the result, does not depend on the device).
+#define DG_RED_BLOCKS 1024
+#define DG_RED_VALS 8
+
+// ---- launchers (return hipError_t as int) -------------------------------
+// Face traces of Q on all six faces of every element.
+int dg_launch_trace(const dg_ctx* c, const double* Q, double* T);
+// RHS: R = dQ/dt using traces Tin of Q.
+int dg_launch_rhs(const dg_ctx* c, const double* Q, const double* Tin, double* R);
+// One RK stage in place; writes the traces of the updated Q to Tout when
+// Tout != nullptr.
+int dg_launch_stage(const dg_ctx* c, double* Q, double* res, const double* Tin,
+                    double* Tout, double a, double b, double dt, int first);
+// Reductions: per-block partials then a fixed-order final pass into
+// red[DG_RED_BLOCKS*DG_RED_VALS .. +DG_RED_VALS).
+int dg_launch_reduce(const dg_ctx* c, const double* Q, double* red);
+// Adjoint RHS.
+int dg_launch_vjp(const dg_ctx* c, const double* Q, const double* gR, double* gQ, char* scratch);
+
+// FP32 matrix-core variants.
+int dg_launch_rhs_f32(const dg_ctx* c, const double* Q, const double* Tin, double* R);
+int dg_launch_stage_f32(const dg_ctx* c, double* Q, double* res, const double* Tin,
+                        double* Tout, double a, double b, double dt, int first);
+bool dg_f32_supported(int N);

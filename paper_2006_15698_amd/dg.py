@@ -1,0 +1,316 @@
+"""ctypes binding of libdg.so: the functions of include/dg.h under the same
+names, taking torch CUDA tensors (or raw device pointers) for device arrays.
+
+Argument marshalling only: tensors are checked for device, dtype, contiguity
+and size, then their data pointers and the current torch stream are handed to
+the C ABI.  Every computation runs in the library's HIP kernels; there is no
+CPU or PyTorch fallback, and importing this module fails if the library is
+missing.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2006_15698_amd.build`")
+
+# torch brings its own HIP runtime (libamdhip64.so under torch/lib, soname
+# libamdhip64.so.7).  Loading torch first makes the dynamic loader resolve
+# libdg.so's libamdhip64.so.7 to that same runtime; loading libdg.so first
+# would map a second HIP/HSA runtime into the process.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+DG_OK = 0
+DG_EINVAL = -1
+DG_EUNSUPPORTED = -2
+DG_EHIP = -3
+DG_EALIAS = -4
+DG_ENONPHYSICAL = -5
+DG_EWORKSPACE = -6
+DG_FP64 = 0
+DG_FP32_MFMA = 1
+
+ERROR_NAMES = {DG_EINVAL: "DG_EINVAL", DG_EUNSUPPORTED: "DG_EUNSUPPORTED", DG_EHIP: "DG_EHIP",
+               DG_EALIAS: "DG_EALIAS", DG_ENONPHYSICAL: "DG_ENONPHYSICAL",
+               DG_EWORKSPACE: "DG_EWORKSPACE"}
+
+_vp, _i, _d, _sz, _i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "dg_create": (_vp, [_i, _i, _i, _i, _d]),
+    "dg_destroy": (None, [_vp]),
+    "dg_last_error": (ctypes.c_char_p, []),
+    "dg_set_domain": (_i, [_vp, _d, _d, _d]),
+    "dg_set_stream": (_i, [_vp, _vp]),
+    "dg_set_precision": (_i, [_vp, _i]),
+    "dg_workspace_bytes": (_sz, [_vp]),
+    "dg_set_workspace": (_i, [_vp, _vp, _sz]),
+    "dg_num_dof": (_i64, [_vp]),
+    "dg_quadrature": (_i, [_i, _dp, _dp]),
+    "dg_rhs": (_i, [_vp, _vp, _vp]),
+    "dg_rk_stage": (_i, [_vp, _i, _vp, _vp, _d]),
+    "dg_rk_step": (_i, [_vp, _vp, _vp, _d]),
+    "dg_rk_steps": (_i, [_vp, _vp, _vp, _d, _i]),
+    "dg_rhs_vjp": (_i, [_vp, _vp, _vp, _vp]),
+    "dg_integrals": (_i, [_vp, _vp, _dp]),
+    "dg_max_wavespeed": (_i, [_vp, _vp, _dp]),
+    "dg_check_state": (_i, [_vp, _vp]),
+    "dg_set_timing": (_i, [_vp, _i]),
+    "dg_timing_read": (_i, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def dg_last_error():
+    return _lib.dg_last_error().decode()
+
+
+def _check(rc):
+    if rc != DG_OK:
+        raise DGError(rc, dg_last_error())
+    return rc
+
+
+def _ptr(x, nd=None):
+    """Device pointer of a torch CUDA tensor (float64, contiguous, numel nd)
+    or of a raw integer address."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("expected a torch tensor or a device address")
+    if not x.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not x.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if nd is not None:
+        if x.dtype != torch.float64:
+            raise ValueError("state arrays are float64")
+        if x.numel() != nd:
+            raise ValueError(f"tensor has {x.numel()} elements, expected {nd}")
+    return x.data_ptr()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---- the C ABI under the same names ---------------------------------------
+def dg_create(nx, ny, nz, p, gamma=1.4):
+    ctx = _lib.dg_create(int(nx), int(ny), int(nz), int(p), float(gamma))
+    if not ctx:
+        raise DGError(DG_EINVAL, dg_last_error())
+    return ctx
+
+
+def dg_destroy(ctx):
+    _lib.dg_destroy(ctx)
+
+
+def dg_set_domain(ctx, Lx, Ly, Lz):
+    return _check(_lib.dg_set_domain(ctx, float(Lx), float(Ly), float(Lz)))
+
+
+def dg_set_stream(ctx, stream=None):
+    return _check(_lib.dg_set_stream(ctx, _stream_ptr(stream)))
+
+
+def dg_set_precision(ctx, mode):
+    return _check(_lib.dg_set_precision(ctx, int(mode)))
+
+
+def dg_workspace_bytes(ctx):
+    return int(_lib.dg_workspace_bytes(ctx))
+
+
+def dg_set_workspace(ctx, ws, nbytes=None):
+    if nbytes is None:
+        nbytes = ws.numel() * ws.element_size()
+    return _check(_lib.dg_set_workspace(ctx, _ptr(ws), int(nbytes)))
+
+
+def dg_num_dof(ctx):
+    return int(_lib.dg_num_dof(ctx))
+
+
+def dg_quadrature(p):
+    n = p + 1
+    xi = (ctypes.c_double * n)()
+    w = (ctypes.c_double * n)()
+    _check(_lib.dg_quadrature(int(p), xi, w))
+    return np.array(xi[:]), np.array(w[:])
+
+
+def _nd(ctx):
+    return 5 * dg_num_dof(ctx)
+
+
+def dg_rhs(ctx, Q, R):
+    nd = _nd(ctx)
+    return _check(_lib.dg_rhs(ctx, _ptr(Q, nd), _ptr(R, nd)))
+
+
+def dg_rk_stage(ctx, s, Q, res, dt):
+    nd = _nd(ctx)
+    return _check(_lib.dg_rk_stage(ctx, int(s), _ptr(Q, nd), _ptr(res, nd), float(dt)))
+
+
+def dg_rk_step(ctx, Q, res, dt):
+    nd = _nd(ctx)
+    return _check(_lib.dg_rk_step(ctx, _ptr(Q, nd), _ptr(res, nd), float(dt)))
+
+
+def dg_rk_steps(ctx, Q, res, dt, nsteps):
+    nd = _nd(ctx)
+    return _check(_lib.dg_rk_steps(ctx, _ptr(Q, nd), _ptr(res, nd), float(dt), int(nsteps)))
+
+
+def dg_rhs_vjp(ctx, Q, gR, gQ):
+    nd = _nd(ctx)
+    return _check(_lib.dg_rhs_vjp(ctx, _ptr(Q, nd), _ptr(gR, nd), _ptr(gQ, nd)))
+
+
+def dg_integrals(ctx, Q):
+    out = (ctypes.c_double * 6)()
+    _check(_lib.dg_integrals(ctx, _ptr(Q, _nd(ctx)), out))
+    return np.array(out[:])
+
+
+def dg_max_wavespeed(ctx, Q):
+    out = ctypes.c_double()
+    _check(_lib.dg_max_wavespeed(ctx, _ptr(Q, _nd(ctx)), ctypes.byref(out)))
+    return out.value
+
+
+def dg_check_state(ctx, Q):
+    """True if the state is physical; False on DG_ENONPHYSICAL."""
+    rc = _lib.dg_check_state(ctx, _ptr(Q, _nd(ctx)))
+    if rc == DG_ENONPHYSICAL:
+        return False
+    _check(rc)
+    return True
+
+
+TIMING_KINDS = ("trace", "stage", "rhs", "vjp", "reduce")
+
+
+def dg_set_timing(ctx, on):
+    return _check(_lib.dg_set_timing(ctx, 1 if on else 0))
+
+
+def dg_timing_read(ctx):
+    """{kind: (milliseconds, launches)} since timing was switched on."""
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int64 * 5)()
+    _check(_lib.dg_timing_read(ctx, ms, cnt))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_KINDS)}
+
+
+# ---- convenience -----------------------------------------------------------
+class Solver:
+    """One periodic mesh on one GPU: owns the context and a torch-allocated
+    workspace, and enqueues every call on the current torch stream."""
+
+    def __init__(self, n, p, L=(1.0, 1.0, 1.0), gamma=1.4, precision=DG_FP64, device=None):
+        import torch
+        if isinstance(n, int):
+            n = (n, n, n)
+        self.n = tuple(int(v) for v in n)
+        self.p = int(p)
+        self.N = self.p + 1
+        self.L = tuple(float(v) for v in L)
+        self.gamma = float(gamma)
+        self.device = torch.device(device or "cuda")
+        self.ctx = dg_create(*self.n, self.p, self.gamma)
+        dg_set_domain(self.ctx, *self.L)
+        dg_set_precision(self.ctx, precision)
+        nbytes = dg_workspace_bytes(self.ctx)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        addr = self.workspace.data_ptr()
+        aligned = (addr + 255) & ~255
+        _check(_lib.dg_set_workspace(self.ctx, aligned, nbytes))
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            dg_destroy(ctx)
+            self.ctx = None
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.n
+        return (5, nz, ny, nx, self.N, self.N, self.N)
+
+    @property
+    def num_dof(self):
+        return dg_num_dof(self.ctx)
+
+    def set_precision(self, mode):
+        dg_set_precision(self.ctx, mode)
+
+    def _s(self):
+        dg_set_stream(self.ctx, None)
+
+    def empty(self):
+        import torch
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    def rhs(self, Q, out=None):
+        out = self.empty() if out is None else out
+        self._s()
+        dg_rhs(self.ctx, Q, out)
+        return out
+
+    def rk_stage(self, s, Q, res, dt):
+        self._s()
+        dg_rk_stage(self.ctx, s, Q, res, dt)
+
+    def step(self, Q, res, dt, nsteps=1):
+        self._s()
+        dg_rk_steps(self.ctx, Q, res, dt, nsteps)
+
+    def rhs_vjp(self, Q, gR, out=None):
+        out = self.empty() if out is None else out
+        self._s()
+        dg_rhs_vjp(self.ctx, Q, gR, out)
+        return out
+
+    def integrals(self, Q):
+        self._s()
+        return dg_integrals(self.ctx, Q)
+
+    def max_wavespeed(self, Q):
+        self._s()
+        return dg_max_wavespeed(self.ctx, Q)
+
+    def dt_cfl(self, Q, cfl):
+        """dt = CFL / ((2p+1) max_d-summed wave rate), computed on the GPU."""
+        return cfl / ((2 * self.p + 1) * self.max_wavespeed(Q))
+
+    def check_state(self, Q):
+        self._s()
+        return dg_check_state(self.ctx, Q)

@@ -1,0 +1,178 @@
+"""GPU parity of the fused LSERK45 stage (RHS + 2N-storage update) against
+the oracle's stepper, plus the stepping invariants of the C ABI."""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.dg import DG
+from oracle import lserk
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def dgm():
+    from paper_2006_15698_amd import dg
+    return dg
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    """max over fields of |a_f - b_f|_inf / |b_f|_inf."""
+    d = np.abs(a - b).reshape(5, -1).max(axis=1)
+    return float(np.max(d / np.abs(b).reshape(5, -1).max(axis=1)))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_stage_by_stage(dgm, p):
+    """Each of the five stages, called one at a time through dg_rk_stage."""
+    import torch
+    n, L = (3, 4, 2), (1.0, 1.2, 0.8)
+    print(f"[rk stages p={p}]", flush=True)
+    Q0 = W.random_smooth(n, p, seed=40 + p, L=L, noise=0.02)
+    ora = DG(n, p, L=L)
+    dt = ora.dt_cfl(Q0, 0.3)
+    s = dgm.Solver(n, p, L=L)
+    Qg = _dev(Q0)
+    rg = torch.full_like(Qg, float("nan"))    # stage 0 must overwrite res
+    Qo, ro = Q0.copy(), np.zeros_like(Q0)
+    for st in range(5):
+        s.rk_stage(st, Qg, rg, dt)
+        lserk.stage(st, Qo, ro, dt, ora.rhs)
+        assert _rel(_host(Qg), Qo) <= TOL
+        assert _rel(_host(rg), ro) <= 1e-11   # res ~ dt R: relative to a small register
+
+
+def test_density_wave_c1_trajectory(dgm):
+    """First workload: 4^3, p = 1, dt from CFL 0.3, 20 steps, compared with
+    the oracle after every step, and against the closed-form solution."""
+    import torch
+    n, p = 4, 1
+    Q0 = W.density_wave(n, p)
+    ora = DG((n, n, n), p)
+    dt = ora.dt_cfl(Q0, 0.3)
+    s = dgm.Solver((n, n, n), p)
+    assert abs(s.dt_cfl(_dev(Q0), 0.3) - dt) <= 1e-14 * dt
+    Qg = _dev(Q0)
+    rg = torch.zeros_like(Qg)
+    Qo, ro = Q0.copy(), np.zeros_like(Q0)
+    for k in range(20):
+        s.step(Qg, rg, dt)
+        lserk.step(Qo, ro, dt, ora.rhs)
+        assert _rel(_host(Qg), Qo) <= TOL, k
+    # velocity and pressure stay uniform (every equation is a multiple of the
+    # mass equation for this state)
+    Qh = _host(Qg)
+    u = Qh[1] / Qh[0]
+    assert np.max(np.abs(u - 1.0)) < 1e-12
+
+
+def test_steps_bitwise_equal_repeated_step(dgm):
+    """dg_rk_steps(n) carries face traces from stage to stage; it must equal
+    n separate dg_rk_step calls bit for bit."""
+    import torch
+    n, p = (5, 3, 4), 3
+    Q0 = _dev(W.random_smooth(n, p, seed=7, noise=0.02))
+    s = dgm.Solver(n, p)
+    dt = 0.2 * s.dt_cfl(Q0, 1.0)
+    Qa, ra = Q0.clone(), torch.zeros_like(Q0)
+    Qb, rb = Q0.clone(), torch.zeros_like(Q0)
+    s.step(Qa, ra, dt, nsteps=4)
+    for _ in range(4):
+        s.step(Qb, rb, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(Qa, Qb) and torch.equal(ra, rb)
+
+
+def test_resume_from_checkpoint_bitwise(dgm):
+    """Q is the only state carried across steps (a_1 = 0 resets res), so a
+    run resumed from a saved Q with a garbage res register is identical."""
+    import torch
+    n, p = (4, 4, 4), 2
+    Q0 = _dev(W.random_smooth(n, p, seed=8))
+    s = dgm.Solver(n, p)
+    dt = 0.2 * s.dt_cfl(Q0, 1.0)
+    Qa, ra = Q0.clone(), torch.zeros_like(Q0)
+    s.step(Qa, ra, dt, nsteps=6)
+    Qb, rb = Q0.clone(), torch.zeros_like(Q0)
+    s.step(Qb, rb, dt, nsteps=3)
+    Qc = Qb.clone()
+    rc = torch.randn_like(Qc)
+    s.step(Qc, rc, dt, nsteps=3)
+    torch.cuda.synchronize()
+    assert torch.equal(Qa, Qc)
+
+
+def test_tgv_c2_steps_vs_oracle(dgm):
+    """Second workload at full size for 3 steps (oracle cost ~20 RHS)."""
+    import torch
+    print("[rk tgv 32^3 p=3, 3 steps]", flush=True)
+    L = (2 * math.pi,) * 3
+    Q0 = W.tgv(32, 3)
+    ora = DG((32, 32, 32), 3, L=L)
+    dt = ora.dt_cfl(Q0, 0.3)
+    s = dgm.Solver((32, 32, 32), 3, L=L)
+    Qg = _dev(Q0)
+    rg = torch.zeros_like(Qg)
+    s.step(Qg, rg, dt, nsteps=3)
+    Qo = lserk.integrate(Q0, dt, 3, ora.rhs)
+    Qh = _host(Qg)
+    # state-relative bar (the state is O(p0) for energy)
+    assert _rel(Qh, Qo) <= TOL
+    # change-relative: the update itself matches
+    dq = np.abs(Qh - Qo).reshape(5, -1).max(axis=1)
+    ch = np.abs(Qo - Q0).reshape(5, -1).max(axis=1)
+    print("change-relative", dq / ch)
+    assert np.all(dq <= 1e-10 * ch)
+
+
+def test_integrals_and_wavespeed(dgm):
+    n, p, L = (5, 4, 3), 3, (1.0, 0.9, 1.2)
+    Q = W.random_smooth(n, p, seed=9, L=L)
+    ora = DG(n, p, L=L)
+    s = dgm.Solver(n, p, L=L)
+    Qd = _dev(Q)
+    I = s.integrals(Qd)
+    Io = ora.integrals(Q)
+    assert np.max(np.abs(I - Io) / np.abs(Io).max()) <= 1e-13
+    assert abs(s.max_wavespeed(Qd) - ora.max_rate(Q)) <= 1e-14 * ora.max_rate(Q)
+    assert s.check_state(Qd)
+    Q2 = Q.copy()
+    Q2[4, 1, 2, 3, 0, 1, 2] = 0.0
+    assert not s.check_state(_dev(Q2))
+    Q3 = Q.copy()
+    Q3[0, 0, 0, 0, 0, 0, 0] = float("nan")
+    assert not s.check_state(_dev(Q3))
+    # bitwise reproducible
+    assert np.array_equal(s.integrals(Qd), I)
+
+
+def test_conservation_over_steps(dgm):
+    """Mass, momentum and energy integrals are conserved to roundoff over RK
+    steps on a periodic mesh (discrete conservation)."""
+    import torch
+    n, p = (6, 6, 6), 3
+    L = (2 * math.pi,) * 3
+    s = dgm.Solver(n, p, L=L)
+    Qd = _dev(W.tgv(6, 3))
+    r = torch.zeros_like(Qd)
+    I0 = s.integrals(Qd)
+    s.step(Qd, r, 0.3 * s.dt_cfl(Qd, 1.0), nsteps=10)
+    I1 = s.integrals(Qd)
+    scale = np.array([I0[0], I0[0], I0[0], I0[0], I0[4]])
+    assert np.all(np.abs(I1[:5] - I0[:5]) <= 1e-13 * scale)
