@@ -138,6 +138,15 @@ int dg_rk_steps(dg_ctx* ctx, double* Q, double* res, double dt, int nsteps);
  * (written) are device arrays in the layout above; gQ must not alias Q or gR. */
 int dg_rhs_vjp(dg_ctx* ctx, const double* Q, const double* gR, double* gQ);
 
+/* Reverse of LSERK45 stage s (0..4) for checkpointed gradients through
+ * time stepping.  Qs is the state that stage s started from; on entry gQ and
+ * gres hold the adjoints of the stage's outputs (Q, res), on return the
+ * adjoints of its inputs:
+ *   g = gres + b_s gQ;   gQ <- gQ + dt (dR/dQ at Qs)^T g;   gres <- a_s g
+ * (a_0 = 0: the input res of stage 0 has zero adjoint).  Device arrays in the
+ * layout above; gQ and gres must not overlap each other or Qs. */
+int dg_rk_stage_vjp(dg_ctx* ctx, int s, const double* Qs, double* gQ, double* gres, double dt);
+
 /* SYNCHRONISING.  Domain integrals by the nodal Gauss-Legendre rule:
  * out[0..4] = integral of the five conserved fields, out[5] = integral of
  * the kinetic energy |rho u|^2/(2 rho).  out is a HOST array of 6 doubles.

@@ -169,6 +169,16 @@ void build_tables(dg_ctx* c) {
     t.w[i] = c->w[i];
     for (int a = 0; a < N; ++a) t.Dh[i * N + a] = c->w[a] * D[a][i] / c->w[i];
   }
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int a = 0; a < N; ++a) {
+      s += t.Dh[i * N + a];
+      t.Dh32[i * N + a] = (float)t.Dh[i * N + a];
+    }
+    t.rs[i] = s;
+    t.lm32[i] = (float)t.lm[i];
+    t.lp32[i] = (float)t.lp[i];
+  }
   const double h[3] = {c->L[0] / c->nx, c->L[1] / c->ny, c->L[2] / c->nz};
   for (int d = 0; d < 3; ++d) {
     t.sc[d] = 2.0 / h[d];
@@ -225,15 +235,17 @@ int run_reduce(dg_ctx* c, const double* Q, double out[DG_RED_VALS]) {
 int stages(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
   // Traces of the initial Q, then `count` stages starting at stage s0; each
   // stage but the last writes the traces of its updated Q for the next.
-  int err = timed(c, TK_TRACE, [&] { return dg_launch_trace(c, Q, trace_buf(c, 0)); });
-  if (err) return hip_fail(err, "trace launch");
   const bool f32 = c->precision == DG_FP32_MFMA;
+  int err = timed(c, TK_TRACE, [&] {
+    return f32 ? dg_launch_trace_f32(c, Q, (char*)trace_buf(c, 0)) : dg_launch_trace(c, Q, trace_buf(c, 0));
+  });
+  if (err) return hip_fail(err, "trace launch");
   for (int g = 0; g < count; ++g) {
     const int s = (s0 + g) % 5;
-    const double* tin = trace_buf(c, g & 1);
+    double* tin = trace_buf(c, g & 1);
     double* tout = g + 1 < count ? trace_buf(c, (g + 1) & 1) : nullptr;
     err = timed(c, TK_STAGE, [&] {
-      return f32 ? dg_launch_stage_f32(c, Q, res, tin, tout, kRKA[s], kRKB[s], dt, s == 0)
+      return f32 ? dg_launch_stage_f32(c, Q, res, (const char*)tin, (char*)tout, kRKA[s], kRKB[s], dt, s == 0)
                  : dg_launch_stage(c, Q, res, tin, tout, kRKA[s], kRKB[s], dt, s == 0);
     });
     if (err) return hip_fail(err, "stage launch");
@@ -259,10 +271,8 @@ DGWorkspace dg_workspace_layout(const dg_ctx* c) {
   L.off_red = L.off_trace1 + L.trace_bytes;
   const size_t red_bytes = align256((DG_RED_BLOCKS + 1) * DG_RED_VALS * sizeof(double));
   L.off_vjp = L.off_red + red_bytes;
-  // adjoint scratch: face-flux adjoints (30 N^2 E) and the lifted trace
-  // adjoints of both sides (2 * 30 N^2 E), plus the state-sized volume part
-  const size_t vjp_bytes = align256(3 * 30 * N2 * (size_t)c->E * sizeof(double)) +
-                           align256(DG_NF * N3 * (size_t)c->E * sizeof(double));
+  // adjoint scratch for the reverse RK stage: two state-sized buffers
+  const size_t vjp_bytes = 2 * align256(DG_NF * N3 * (size_t)c->E * sizeof(double));
   L.total = L.off_vjp + vjp_bytes;
   return L;
 }
@@ -412,11 +422,13 @@ int dg_rhs(dg_ctx* c, const double* Q, double* R) {
   if (rc) return rc;
   rc = check_state_pair(c, Q, "Q", R, "R");
   if (rc) return rc;
-  int err = timed(c, TK_TRACE, [&] { return dg_launch_trace(c, Q, trace_buf(c, 0)); });
+  const bool f32 = c->precision == DG_FP32_MFMA;
+  int err = timed(c, TK_TRACE, [&] {
+    return f32 ? dg_launch_trace_f32(c, Q, (char*)trace_buf(c, 0)) : dg_launch_trace(c, Q, trace_buf(c, 0));
+  });
   if (err) return hip_fail(err, "trace launch");
   err = timed(c, TK_RHS, [&] {
-    return c->precision == DG_FP32_MFMA ? dg_launch_rhs_f32(c, Q, trace_buf(c, 0), R)
-                                        : dg_launch_rhs(c, Q, trace_buf(c, 0), R);
+    return f32 ? dg_launch_rhs_f32(c, Q, (const char*)trace_buf(c, 0), R) : dg_launch_rhs(c, Q, trace_buf(c, 0), R);
   });
   if (err) return hip_fail(err, "rhs launch");
   return DG_OK;
@@ -452,10 +464,30 @@ int dg_rhs_vjp(dg_ctx* c, const double* Q, const double* gR, double* gQ) {
   if (!Q || !gR || !gQ) return fail(DG_EINVAL, "NULL array");
   if (overlap(Q, gQ, state_bytes(c))) return fail(DG_EALIAS, "gQ overlaps Q");
   if (overlap(gR, gQ, state_bytes(c))) return fail(DG_EALIAS, "gQ overlaps gR");
-  const DGWorkspace L = dg_workspace_layout(c);
   int err = timed(c, TK_VJP, [&] { return dg_launch_vjp(c, Q, gR, gQ, c->ws); });
-  (void)L;
   if (err) return hip_fail(err, "vjp launch");
+  return DG_OK;
+}
+
+int dg_rk_stage_vjp(dg_ctx* c, int s, const double* Qs, double* gQ, double* gres, double dt) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (s < 0 || s > 4) return fail(DG_EINVAL, "stage must be 0..4 (got %d)", s);
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  if (!Qs || !gQ || !gres) return fail(DG_EINVAL, "NULL array");
+  const size_t sb = state_bytes(c);
+  if (overlap(gQ, gres, sb)) return fail(DG_EALIAS, "gQ overlaps gres");
+  if (overlap(Qs, gQ, sb) || overlap(Qs, gres, sb)) return fail(DG_EALIAS, "adjoint overlaps Qs");
+  const DGWorkspace L = dg_workspace_layout(c);
+  double* gtot = (double*)(c->ws + L.off_vjp);
+  double* v = (double*)(c->ws + L.off_vjp + align256(sb));
+  const int64_t n = (int64_t)(sb / sizeof(double));
+  int err = timed(c, TK_VJP, [&] { return dg_launch_axpy(c, n, gres, kRKB[s], gQ, gtot); });
+  if (err) return hip_fail(err, "axpy launch");
+  err = timed(c, TK_VJP, [&] { return dg_launch_vjp(c, Qs, gtot, v, c->ws); });
+  if (err) return hip_fail(err, "vjp launch");
+  err = timed(c, TK_VJP, [&] { return dg_launch_rk_reverse(c, n, v, dt, kRKA[s], gtot, gQ, gres); });
+  if (err) return hip_fail(err, "reverse stage launch");
   return DG_OK;
 }
 

@@ -20,6 +20,11 @@ struct DGTables {
   double liftm[DG_MAXN];         // l_i(-1) / w_i: surface term of Eq. (5)
   double liftp[DG_MAXN];         // l_i(+1) / w_i   lifted by M^{-1}
   double w[DG_MAXN];             // Gauss-Legendre weights
+  double rs[DG_MAXN];            // rs[i] = sum_a Dh[i*N+a] (free-stream identity:
+                                 // (l_i(1) - l_i(-1)) / w_i up to rounding)
+  float Dh32[DG_MAXN * DG_MAXN]; // Dh rounded to FP32 (matrix-core variant)
+  float lm32[DG_MAXN];           // l_i(-1), l_i(+1) rounded to FP32
+  float lp32[DG_MAXN];
   double sc[3];                  // 2 / h_d (reference-to-physical metric)
   double hinv[3];                // 1 / h_d
   double J;                      // h_x h_y h_z / 8 (volume Jacobian)
@@ -49,7 +54,7 @@ struct DGWorkspace {
   size_t trace_bytes;   // one face-trace buffer: 30 * N^2 * E doubles
   size_t off_trace0, off_trace1;
   size_t off_red;       // reduction partials
-  size_t off_vjp;       // adjoint scratch
+  size_t off_vjp;       // adjoint scratch: two state-sized buffers
   size_t total;
 };
 DGWorkspace dg_workspace_layout(const dg_ctx* c);
@@ -74,8 +79,15 @@ int dg_launch_reduce(const dg_ctx* c, const double* Q, double* red);
 // Adjoint RHS.
 int dg_launch_vjp(const dg_ctx* c, const double* Q, const double* gR, double* gQ, char* scratch);
 
-// FP32 matrix-core variants.
-int dg_launch_rhs_f32(const dg_ctx* c, const double* Q, const double* Tin, double* R);
-int dg_launch_stage_f32(const dg_ctx* c, double* Q, double* res, const double* Tin,
-                        double* Tout, double a, double b, double dt, int first);
+int dg_launch_axpy(const dg_ctx* c, int64_t n, const double* x, double b, const double* y, double* out);
+int dg_launch_rk_reverse(const dg_ctx* c, int64_t n, const double* v, double dt, double a, const double* gtot,
+                         double* gQ, double* gres);
+
+// FP32 matrix-core variants.  Their trace buffers hold FP32 deviations
+// [face][field][E][N^2] followed (256-aligned) by FP64 anchors [field][E];
+// they fit in the same workspace regions as the FP64 traces.
+int dg_launch_trace_f32(const dg_ctx* c, const double* Q, char* buf);
+int dg_launch_rhs_f32(const dg_ctx* c, const double* Q, const char* tin, double* R);
+int dg_launch_stage_f32(const dg_ctx* c, double* Q, double* res, const char* tin, char* tout, double a,
+                        double b, double dt, int first);
 bool dg_f32_supported(int N);

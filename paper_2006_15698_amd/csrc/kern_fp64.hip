@@ -63,35 +63,42 @@ __device__ __forceinline__ int neighbour(const DGTables& tb, int e, int d, int d
   return e + (z - ez) * nx * ny;
 }
 
-// Local Lax-Friedrichs flux across a face with normal +e_d (Section II-B):
-// F* = (F^d(qm) + F^d(qp))/2 - lambda/2 (qp - qm),
-// lambda = max(|u_d-| + c-, |u_d+| + c+).  Ties pick the - side.
-__device__ __forceinline__ void lf_flux(const double* qm, const double* qp, int d,
-                                        double gamma, double gm1, double* out) {
+// Local Lax-Friedrichs flux across a face with normal +e_D (Section II-B):
+// F* = (F^D(qm) + F^D(qp))/2 - lambda/2 (qp - qm),
+// lambda = max(|u_D-| + c-, |u_D+| + c+).  Ties pick the - side.  The
+// direction is a template parameter so that every array index is static
+// (a runtime index would force qm/qp into scratch memory).
+template <int D>
+__device__ __forceinline__ void lf_flux_d(const double* qm, const double* qp, double gamma, double gm1,
+                                          double* out) {
   const double rm = 1.0 / qm[0];
   const double rp = 1.0 / qp[0];
-  const double mnm = d == 0 ? qm[1] : (d == 1 ? qm[2] : qm[3]);
-  const double mnp = d == 0 ? qp[1] : (d == 1 ? qp[2] : qp[3]);
-  const double unm = mnm * rm;
-  const double unp = mnp * rp;
+  const double unm = qm[1 + D] * rm;
+  const double unp = qp[1 + D] * rp;
   const double pm = gm1 * (qm[4] - 0.5 * (qm[1] * qm[1] + qm[2] * qm[2] + qm[3] * qm[3]) * rm);
   const double pp = gm1 * (qp[4] - 0.5 * (qp[1] * qp[1] + qp[2] * qp[2] + qp[3] * qp[3]) * rp);
   const double lm = fabs(unm) + sqrt(gamma * pm * rm);
   const double lp = fabs(unp) + sqrt(gamma * pp * rp);
   const double lam = lm >= lp ? lm : lp;
   double fm[5], fp[5];
-  fm[0] = mnm;
-  fp[0] = mnp;
-  fm[1] = qm[1] * unm + (d == 0 ? pm : 0.0);
-  fp[1] = qp[1] * unp + (d == 0 ? pp : 0.0);
-  fm[2] = qm[2] * unm + (d == 1 ? pm : 0.0);
-  fp[2] = qp[2] * unp + (d == 1 ? pp : 0.0);
-  fm[3] = qm[3] * unm + (d == 2 ? pm : 0.0);
-  fp[3] = qp[3] * unp + (d == 2 ? pp : 0.0);
+  fm[0] = qm[1 + D];
+  fp[0] = qp[1 + D];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    fm[1 + k] = qm[1 + k] * unm + (k == D ? pm : 0.0);
+    fp[1 + k] = qp[1 + k] * unp + (k == D ? pp : 0.0);
+  }
   fm[4] = (qm[4] + pm) * unm;
   fp[4] = (qp[4] + pp) * unp;
 #pragma unroll
   for (int f = 0; f < 5; ++f) out[f] = 0.5 * (fm[f] + fp[f]) - 0.5 * lam * (qp[f] - qm[f]);
+}
+
+__device__ __forceinline__ void lf_flux(const double* qm, const double* qp, int d, double gamma, double gm1,
+                                        double* out) {
+  if (d == 0) lf_flux_d<0>(qm, qp, gamma, gm1, out);
+  else if (d == 1) lf_flux_d<1>(qm, qp, gamma, gm1, out);
+  else lf_flux_d<2>(qm, qp, gamma, gm1, out);
 }
 
 // Trace of one field on face (d, side) at tangential point pt: sum over the
@@ -251,8 +258,14 @@ k_stage(DGTables tb, double* __restrict__ Q, double* __restrict__ RR,
       const double* coef = side ? sLp : sLm;
 #pragma unroll
       for (int f = 0; f < 5; ++f) own[f] = line_trace<N>(&sQ[f][fel * N3], coef, d, pt);
-      if (side) lf_flux(own, nb[u], d, tb.gamma, tb.gm1, fs);
-      else lf_flux(nb[u], own, d, tb.gamma, tb.gm1, fs);
+      // select values (not pointers) so that nb and own stay in registers
+      double qm[5], qp[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        qm[f] = side ? own[f] : nb[u][f];
+        qp[f] = side ? nb[u][f] : own[f];
+      }
+      lf_flux(qm, qp, d, tb.gamma, tb.gm1, fs);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sH[face][f][fel * N2 + pt] = fs[f];
     }

@@ -60,6 +60,7 @@ _SIGS = {
     "dg_rk_step": (_i, [_vp, _vp, _vp, _d]),
     "dg_rk_steps": (_i, [_vp, _vp, _vp, _d, _i]),
     "dg_rhs_vjp": (_i, [_vp, _vp, _vp, _vp]),
+    "dg_rk_stage_vjp": (_i, [_vp, _i, _vp, _vp, _vp, _d]),
     "dg_integrals": (_i, [_vp, _vp, _dp]),
     "dg_max_wavespeed": (_i, [_vp, _vp, _dp]),
     "dg_check_state": (_i, [_vp, _vp]),
@@ -194,6 +195,11 @@ def dg_rhs_vjp(ctx, Q, gR, gQ):
     return _check(_lib.dg_rhs_vjp(ctx, _ptr(Q, nd), _ptr(gR, nd), _ptr(gQ, nd)))
 
 
+def dg_rk_stage_vjp(ctx, s, Qs, gQ, gres, dt):
+    nd = _nd(ctx)
+    return _check(_lib.dg_rk_stage_vjp(ctx, int(s), _ptr(Qs, nd), _ptr(gQ, nd), _ptr(gres, nd), float(dt)))
+
+
 def dg_integrals(ctx, Q):
     out = (ctypes.c_double * 6)()
     _check(_lib.dg_integrals(ctx, _ptr(Q, _nd(ctx)), out))
@@ -314,3 +320,82 @@ class Solver:
     def check_state(self, Q):
         self._s()
         return dg_check_state(self.ctx, Q)
+
+
+# ---- differentiation -------------------------------------------------------
+class RHS(torch.autograd.Function):
+    """R = dQ/dt as an autograd function: forward dg_rhs, backward dg_rhs_vjp
+    (the hand-written adjoint kernel)."""
+
+    @staticmethod
+    def forward(ctx, Q, solver):
+        R = solver.rhs(Q.detach().contiguous())
+        ctx.save_for_backward(Q)
+        ctx.solver = solver
+        return R
+
+    @staticmethod
+    def backward(ctx, gR):
+        (Q,) = ctx.saved_tensors
+        gQ = ctx.solver.rhs_vjp(Q.detach().contiguous(), gR.contiguous())
+        return gQ, None
+
+
+def rk_gradient(solver, Q0, dt, nsteps, objective_grad, every=8):
+    """Gradient of an objective J(Q_nsteps) with respect to Q0 through
+    ``nsteps`` LSERK45 steps, with Q checkpointed every ``every`` steps.
+
+    objective_grad(Q) must return dJ/dQ at the final state.  Forward: one
+    pass storing Q at every ``every``-th step.  Reverse, segment by segment:
+    recompute the 25..40 stage inputs of the segment from its checkpoint
+    (dg_rk_stage, bitwise equal to the forward pass), then run the stages
+    backwards through dg_rk_stage_vjp.  Returns (J-gradient, final state)."""
+    ckpts = []
+    Q = Q0.detach().clone()
+    res = torch.zeros_like(Q)
+    for n in range(nsteps):
+        if n % every == 0:
+            ckpts.append(Q.clone())
+        solver.step(Q, res, dt)
+    Qfinal = Q
+    gQ = objective_grad(Qfinal).contiguous().clone()
+    gres = torch.zeros_like(gQ)
+    solver._s()
+    for seg in reversed(range(len(ckpts))):
+        n0 = seg * every
+        n1 = min(n0 + every, nsteps)
+        Q = ckpts[seg].clone()
+        res = torch.zeros_like(Q)
+        inputs = []
+        for n in range(n0, n1):
+            for s in range(5):
+                inputs.append((s, Q.clone()))
+                solver.rk_stage(s, Q, res, dt)
+        for s, Qs in reversed(inputs):
+            dg_rk_stage_vjp(solver.ctx, s, Qs, gQ, gres, dt)
+    return gQ, Qfinal
+
+
+def kinetic_energy_weights(solver):
+    """J w_i w_j w_k per node, shaped like one field of the state (for
+    objectives built from the kinetic energy |rho u|^2 / (2 rho))."""
+    xi, w = dg_quadrature(solver.p)
+    nx, ny, nz = solver.n
+    hx, hy, hz = (solver.L[0] / nx, solver.L[1] / ny, solver.L[2] / nz)
+    w3 = np.einsum("k,j,i->kji", w, w, w) * (hx * hy * hz / 8.0)
+    wt = torch.from_numpy(np.ascontiguousarray(w3)).to(solver.device)
+    return wt.reshape(1, 1, 1, solver.N, solver.N, solver.N).expand(nz, ny, nx, -1, -1, -1)
+
+
+def kinetic_energy_grad(solver):
+    """d/dQ of the integrated kinetic energy sum J w |rho u|^2 / (2 rho)."""
+    wt = kinetic_energy_weights(solver)
+
+    def grad(Q):
+        rho, m = Q[0], Q[1:4]
+        u = m / rho
+        g = torch.zeros_like(Q)
+        g[0] = -0.5 * (u * u).sum(0) * wt
+        g[1:4] = u * wt
+        return g
+    return grad
