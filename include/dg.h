@@ -161,6 +161,50 @@ int dg_max_wavespeed(dg_ctx* ctx, const double* Q, double* out);
  * p > 0; DG_ENONPHYSICAL otherwise. */
 int dg_check_state(dg_ctx* ctx, const double* Q);
 
+/* ---- batched independent meshes ---------------------------------------
+ * Many independent periodic meshes of uneven size and degree advanced
+ * together: one persistent launch per RK stage walks a work list of
+ * (mesh, element block) items, with a per-degree code path and per-degree
+ * elements-per-workgroup tile (dg_batch_set_tile).  The arithmetic on every
+ * element is the one of the single-mesh entry points above, so each mesh's
+ * result is bitwise that of a single-mesh context on the same state.
+ * State layout: one device array holding the meshes back to back; mesh i
+ * occupies doubles [dg_batch_offset(b, i), dg_batch_offset(b, i + 1)) in the
+ * single-mesh layout [field][ez][ey][ex][k][j][i]. */
+typedef struct dg_batch dg_batch;
+
+/* count >= 1 meshes; n[3i..3i+2] = (nx, ny, nz) and p[i] (1..5) of mesh i,
+ * L[3i..3i+2] its domain lengths (HOST arrays).  NULL on error. */
+dg_batch* dg_batch_create(int count, const int* n, const int* p, const double* L, double gamma);
+void dg_batch_destroy(dg_batch* b);
+int dg_batch_set_stream(dg_batch* b, void* hip_stream);
+/* FP64 (default) or FP32 matrix-core contractions for every mesh. */
+int dg_batch_set_precision(dg_batch* b, int mode);
+/* Elements per workgroup for degree p (values the build provides: see
+ * dg_batch_tile_options); changes the work list, so call it before
+ * dg_batch_set_workspace. */
+int dg_batch_set_tile(dg_batch* b, int p, int epb);
+/* Up to max tile sizes available for degree p into out[]; returns count. */
+int dg_batch_tile_options(int p, int* out, int max);
+/* Doubles before mesh i's block (i = count gives the total length). */
+int64_t dg_batch_offset(const dg_batch* b, int i);
+size_t dg_batch_workspace_bytes(const dg_batch* b);
+/* Caller-owned device workspace (256-byte aligned).  SYNCHRONISING: copies
+ * the per-mesh tables and the work list into it. */
+int dg_batch_set_workspace(dg_batch* b, void* dptr, size_t bytes);
+/* Per-mesh time steps dt[count] (HOST).  SYNCHRONISING (copied to the
+ * workspace, where the captured graphs read them). */
+int dg_batch_set_dt(dg_batch* b, const double* dt);
+/* R = dQ/dt of every mesh. */
+int dg_batch_rhs(dg_batch* b, const double* Q, double* R);
+/* nsteps LSERK45 steps of every mesh with its own dt: one trace launch,
+ * then one persistent launch per stage. */
+int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps);
+/* Same result as dg_batch_rk_steps, with the five stage launches of a step
+ * replayed from HIP graphs (captured on first use for this (Q, res) pair and
+ * step parity; recaptured when the pointers change). */
+int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps);
+
 /* Opt-in per-launch timing for benchmarks.  While on, the context brackets
  * every kernel it launches with HIP events on its stream (a few microseconds
  * of overhead per launch).  Kinds: 0 face-trace kernel, 1 RK stage kernel,

@@ -1,0 +1,363 @@
+// Host side of the batched multi-mesh entry points (dg_batch_* in dg.h).
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dg_batch.h"
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct dg_batch {
+  int count = 0;
+  double gamma = 1.4;
+  std::vector<DGBatchInst> inst;   // host copy (tables, offsets, dt)
+  std::vector<int64_t> qoff;       // count + 1
+  int epb_for_N[DG_MAXN + 1] = {0};
+  std::vector<int2> items;
+  size_t trace_set_bytes = 0;
+  hipStream_t stream = nullptr;
+  int precision = DG_FP64;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool uploaded = false;
+  // graphs: [parity] for one step each
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  const double* gQ = nullptr;
+  const double* gR = nullptr;
+  int gprec = -1;
+  unsigned grid = 0;
+};
+
+namespace {
+
+struct Layout {
+  size_t off_inst, off_items, off_t0, off_t1, total;
+};
+
+Layout layout(const dg_batch* b) {
+  Layout L;
+  L.off_inst = 0;
+  L.off_items = al256(sizeof(DGBatchInst) * b->count);
+  L.off_t0 = L.off_items + al256(sizeof(int2) * b->items.size());
+  L.off_t1 = L.off_t0 + al256(b->trace_set_bytes);
+  L.total = L.off_t1 + al256(b->trace_set_bytes);
+  return L;
+}
+
+void build_items(dg_batch* b) {
+  b->items.clear();
+  for (int i = 0; i < b->count; ++i) {
+    DGBatchInst& I = b->inst[i];
+    I.epb = b->epb_for_N[I.N];
+    for (int e0 = 0; e0 < I.tab.E; e0 += I.epb) b->items.push_back(make_int2(i, e0));
+  }
+  b->uploaded = false;
+}
+
+void drop_graphs(dg_batch* b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->gexec[k]) (void)hipGraphExecDestroy(b->gexec[k]);
+    b->gexec[k] = nullptr;
+  }
+  b->gQ = b->gR = nullptr;
+}
+
+DGBatchLaunch launch_of(const dg_batch* b, hipStream_t s) {
+  const Layout L = layout(b);
+  DGBatchLaunch l;
+  l.inst = (const DGBatchInst*)(b->ws + L.off_inst);
+  l.items = (const int2*)(b->ws + L.off_items);
+  l.nitems = (int)b->items.size();
+  l.grid = b->grid;
+  l.stream = s;
+  l.f32 = b->precision == DG_FP32_MFMA;
+  return l;
+}
+
+int ready(dg_batch* b) {
+  if (!b) return dg_set_error(DG_EINVAL, "NULL batch");
+  if (!b->ws) return dg_set_error(DG_EWORKSPACE, "no workspace set (need %zu bytes)", layout(b).total);
+  if (!b->uploaded) return dg_set_error(DG_EWORKSPACE, "workspace not initialised (call dg_batch_set_workspace)");
+  return DG_OK;
+}
+
+int hipfail(int err, const char* what) {
+  return dg_set_error(DG_EHIP, "%s: HIP error %d (%s)", what, err, hipGetErrorString((hipError_t)err));
+}
+
+// Launch the five stages of one step with the given trace parity on stream s.
+int launch_step(dg_batch* b, hipStream_t s, int parity, double* Q, double* res) {
+  const Layout L = layout(b);
+  char* T[2] = {b->ws + L.off_t0, b->ws + L.off_t1};
+  const DGBatchLaunch l = launch_of(b, s);
+  for (int st = 0; st < 5; ++st) {
+    const int g = parity + st;
+    int err = dg_batch_launch_stage(l, 2, Q, res, T[g & 1], T[(g + 1) & 1], kDgRKA[st], kDgRKB[st], st == 0);
+    if (err) return err;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_batch* dg_batch_create(int count, const int* n, const int* p, const double* L, double gamma) {
+  if (count < 1 || !n || !p || !L) {
+    dg_set_error(DG_EINVAL, "need count >= 1 and non-NULL n, p, L");
+    return nullptr;
+  }
+  if (!(gamma > 1.0) || !std::isfinite(gamma)) {
+    dg_set_error(DG_EINVAL, "gamma must be finite and > 1");
+    return nullptr;
+  }
+  dg_batch* b = new (std::nothrow) dg_batch;
+  if (!b) {
+    dg_set_error(DG_EINVAL, "out of host memory");
+    return nullptr;
+  }
+  b->count = count;
+  b->gamma = gamma;
+  b->inst.resize(count);
+  b->qoff.resize(count + 1);
+  for (int N = 1; N <= DG_MAXN; ++N) {
+    int opts[16];
+    const int k = dg_batch_tile_list(N, opts, 16);
+    b->epb_for_N[N] = k ? opts[k - 1] : 0;   // default: the largest tile
+  }
+  int64_t q = 0;
+  size_t t = 0;
+  for (int i = 0; i < count; ++i) {
+    const int nx = n[3 * i], ny = n[3 * i + 1], nz = n[3 * i + 2];
+    const int64_t E = (int64_t)nx * ny * nz;
+    if (nx < 1 || ny < 1 || nz < 1 || E > 0x7fffffffLL) {
+      dg_set_error(DG_EINVAL, "mesh %d: bad size %d x %d x %d", i, nx, ny, nz);
+      delete b;
+      return nullptr;
+    }
+    if (p[i] < 1 || p[i] > 5) {
+      dg_set_error(DG_EUNSUPPORTED, "mesh %d: batched degrees are 1..5 (got %d)", i, p[i]);
+      delete b;
+      return nullptr;
+    }
+    const double Li[3] = {L[3 * i], L[3 * i + 1], L[3 * i + 2]};
+    if (!(Li[0] > 0) || !(Li[1] > 0) || !(Li[2] > 0)) {
+      dg_set_error(DG_EINVAL, "mesh %d: domain lengths must be > 0", i);
+      delete b;
+      return nullptr;
+    }
+    DGBatchInst& I = b->inst[i];
+    std::memset(&I, 0, sizeof(I));
+    double xi[DG_MAXN], w[DG_MAXN];
+    dg_build_tables(nx, ny, nz, p[i], gamma, Li, &I.tab, xi, w);
+    I.N = p[i] + 1;
+    const int64_t N3 = (int64_t)I.N * I.N * I.N;
+    I.qoff = q;
+    b->qoff[i] = q;
+    q += 5 * E * N3;
+    I.toff = (int64_t)t;
+    t += al256((size_t)30 * I.N * I.N * (size_t)E * sizeof(double));
+    I.dt = 0.0;
+  }
+  b->qoff[count] = q;
+  b->trace_set_bytes = t;
+  build_items(b);
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) {
+    b->grid = (unsigned)(ncu * dg_batch_blocks_per_cu(0));
+  } else {
+    b->grid = 1024;
+  }
+  return b;
+}
+
+void dg_batch_destroy(dg_batch* b) {
+  if (!b) return;
+  drop_graphs(b);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  delete b;
+}
+
+int dg_batch_set_stream(dg_batch* b, void* s) {
+  if (!b) return dg_set_error(DG_EINVAL, "NULL batch");
+  b->stream = (hipStream_t)s;
+  return DG_OK;
+}
+
+int dg_batch_set_precision(dg_batch* b, int mode) {
+  if (!b) return dg_set_error(DG_EINVAL, "NULL batch");
+  if (mode != DG_FP64 && mode != DG_FP32_MFMA) return dg_set_error(DG_EINVAL, "unknown precision mode %d", mode);
+  if (mode != b->precision) drop_graphs(b);
+  b->precision = mode;
+  return DG_OK;
+}
+
+int dg_batch_tile_options(int p, int* out, int max) {
+  if (p < 0 || p >= DG_MAXN || !out || max < 0) return 0;
+  return dg_batch_tile_list(p + 1, out, max);
+}
+
+int dg_batch_set_tile(dg_batch* b, int p, int epb) {
+  if (!b) return dg_set_error(DG_EINVAL, "NULL batch");
+  if (p < 1 || p > 5) return dg_set_error(DG_EINVAL, "degree must be 1..5");
+  int opts[16];
+  const int k = dg_batch_tile_list(p + 1, opts, 16);
+  bool ok = false;
+  for (int i = 0; i < k; ++i) ok = ok || opts[i] == epb;
+  if (!ok) return dg_set_error(DG_EUNSUPPORTED, "tile %d not built for p=%d", epb, p);
+  b->epb_for_N[p + 1] = epb;
+  build_items(b);
+  drop_graphs(b);
+  b->ws = nullptr;   // the work list changed size: a workspace must be set again
+  b->ws_bytes = 0;
+  return DG_OK;
+}
+
+int64_t dg_batch_offset(const dg_batch* b, int i) {
+  if (!b || i < 0 || i > b->count) return -1;
+  return b->qoff[i];
+}
+
+size_t dg_batch_workspace_bytes(const dg_batch* b) {
+  if (!b) return 0;
+  return layout(b).total;
+}
+
+int dg_batch_set_workspace(dg_batch* b, void* dptr, size_t bytes) {
+  if (!b) return dg_set_error(DG_EINVAL, "NULL batch");
+  if (!dptr) return dg_set_error(DG_EINVAL, "NULL workspace");
+  if (((uintptr_t)dptr) & 255) return dg_set_error(DG_EINVAL, "workspace not 256-byte aligned");
+  const Layout L = layout(b);
+  if (bytes < L.total) return dg_set_error(DG_EWORKSPACE, "workspace %zu bytes < %zu", bytes, L.total);
+  b->ws = (char*)dptr;
+  b->ws_bytes = bytes;
+  drop_graphs(b);
+  int err = (int)hipMemcpy(b->ws + L.off_inst, b->inst.data(), sizeof(DGBatchInst) * b->count, hipMemcpyHostToDevice);
+  if (err) return hipfail(err, "upload tables");
+  err = (int)hipMemcpy(b->ws + L.off_items, b->items.data(), sizeof(int2) * b->items.size(), hipMemcpyHostToDevice);
+  if (err) return hipfail(err, "upload work list");
+  b->uploaded = true;
+  return DG_OK;
+}
+
+int dg_batch_set_dt(dg_batch* b, const double* dt) {
+  int rc = ready(b);
+  if (rc) return rc;
+  if (!dt) return dg_set_error(DG_EINVAL, "NULL dt");
+  for (int i = 0; i < b->count; ++i) {
+    if (!std::isfinite(dt[i])) return dg_set_error(DG_EINVAL, "dt[%d] not finite", i);
+    b->inst[i].dt = dt[i];
+  }
+  const Layout L = layout(b);
+  int err = (int)hipStreamSynchronize(b->stream);
+  if (err) return hipfail(err, "sync before dt upload");
+  err = (int)hipMemcpy(b->ws + L.off_inst, b->inst.data(), sizeof(DGBatchInst) * b->count, hipMemcpyHostToDevice);
+  if (err) return hipfail(err, "upload dt");
+  return DG_OK;
+}
+
+int dg_batch_rhs(dg_batch* b, const double* Q, double* R) {
+  int rc = ready(b);
+  if (rc) return rc;
+  if (!Q || !R) return dg_set_error(DG_EINVAL, "NULL array");
+  const size_t sb = (size_t)b->qoff[b->count] * sizeof(double);
+  if ((const char*)Q < (const char*)R + sb && (const char*)R < (const char*)Q + sb)
+    return dg_set_error(DG_EALIAS, "R overlaps Q");
+  const Layout L = layout(b);
+  const DGBatchLaunch l = launch_of(b, b->stream);
+  int err = dg_batch_launch_trace(l, Q, b->ws + L.off_t0);
+  if (err) return hipfail(err, "batch trace launch");
+  err = dg_batch_launch_stage(l, 0, const_cast<double*>(Q), R, b->ws + L.off_t0, nullptr, 0.0, 0.0, 0);
+  if (err) return hipfail(err, "batch rhs launch");
+  return DG_OK;
+}
+
+int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps) {
+  int rc = ready(b);
+  if (rc) return rc;
+  if (!Q || !res) return dg_set_error(DG_EINVAL, "NULL array");
+  if (nsteps < 0) return dg_set_error(DG_EINVAL, "nsteps must be >= 0");
+  const size_t sb = (size_t)b->qoff[b->count] * sizeof(double);
+  if ((char*)Q < (char*)res + sb && (char*)res < (char*)Q + sb) return dg_set_error(DG_EALIAS, "res overlaps Q");
+  if (nsteps == 0) return DG_OK;
+  const Layout L = layout(b);
+  const DGBatchLaunch l = launch_of(b, b->stream);
+  int err = dg_batch_launch_trace(l, Q, b->ws + L.off_t0);
+  if (err) return hipfail(err, "batch trace launch");
+  for (int n = 0; n < nsteps; ++n) {
+    err = launch_step(b, b->stream, (5 * n) & 1, Q, res);
+    if (err) return hipfail(err, "batch stage launch");
+  }
+  return DG_OK;
+}
+
+int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps) {
+  int rc = ready(b);
+  if (rc) return rc;
+  if (!Q || !res) return dg_set_error(DG_EINVAL, "NULL array");
+  if (nsteps < 0) return dg_set_error(DG_EINVAL, "nsteps must be >= 0");
+  const size_t sb = (size_t)b->qoff[b->count] * sizeof(double);
+  if ((char*)Q < (char*)res + sb && (char*)res < (char*)Q + sb) return dg_set_error(DG_EALIAS, "res overlaps Q");
+  if (nsteps == 0) return DG_OK;
+  int err;
+  if (!b->gstream) {
+    err = (int)hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+    if (err) return hipfail(err, "graph stream");
+    err = (int)hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (err) return hipfail(err, "graph event");
+    err = (int)hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (err) return hipfail(err, "graph event");
+  }
+  if (b->gQ != Q || b->gR != res || b->gprec != b->precision) drop_graphs(b);
+  // order after the caller's stream
+  err = (int)hipEventRecord(b->ev_in, b->stream);
+  if (err) return hipfail(err, "event record");
+  err = (int)hipStreamWaitEvent(b->gstream, b->ev_in, 0);
+  if (err) return hipfail(err, "stream wait");
+  for (int par = 0; par < 2; ++par) {
+    if (b->gexec[par]) continue;
+    hipGraph_t graph = nullptr;
+    err = (int)hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
+    if (err) return hipfail(err, "begin capture");
+    int lerr = launch_step(b, b->gstream, par, Q, res);
+    err = (int)hipStreamEndCapture(b->gstream, &graph);
+    if (lerr) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hipfail(lerr, "capture launch");
+    }
+    if (err) return hipfail(err, "end capture");
+    err = (int)hipGraphInstantiate(&b->gexec[par], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (err) return hipfail(err, "graph instantiate");
+  }
+  b->gQ = Q;
+  b->gR = res;
+  b->gprec = b->precision;
+  const Layout L = layout(b);
+  const DGBatchLaunch l = launch_of(b, b->gstream);
+  err = dg_batch_launch_trace(l, Q, b->ws + L.off_t0);
+  if (err) return hipfail(err, "batch trace launch");
+  for (int n = 0; n < nsteps; ++n) {
+    err = (int)hipGraphLaunch(b->gexec[(5 * n) & 1], b->gstream);
+    if (err) return hipfail(err, "graph launch");
+  }
+  err = (int)hipEventRecord(b->ev_out, b->gstream);
+  if (err) return hipfail(err, "event record");
+  err = (int)hipStreamWaitEvent(b->stream, b->ev_out, 0);
+  if (err) return hipfail(err, "stream wait");
+  return DG_OK;
+}
+
+}  // extern "C"

@@ -10,6 +10,7 @@
 #include <new>
 #include <vector>
 
+#include "dg_batch.h"
 #include "dg_internal.h"
 
 namespace {
@@ -131,66 +132,7 @@ void gauss_legendre(int n, double* x, double* w) {
 }
 
 void build_tables(dg_ctx* c) {
-  const int N = c->N;
-  DGTables& t = c->tab;
-  std::memset(&t, 0, sizeof(t));
-  gauss_legendre(N, c->xi, c->w);
-  // barycentric weights 1 / prod_{m != i} (xi_i - xi_m)
-  double bw[DG_MAXN];
-  for (int i = 0; i < N; ++i) {
-    double prod = 1.0;
-    for (int m = 0; m < N; ++m)
-      if (m != i) prod *= (c->xi[i] - c->xi[m]);
-    bw[i] = 1.0 / prod;
-  }
-  // D[a][i] = l_i'(xi_a): off-diagonal (bw_i / bw_a) / (xi_a - xi_i),
-  // diagonal from the zero row sum (derivative of a constant).
-  double D[DG_MAXN][DG_MAXN];
-  for (int a = 0; a < N; ++a) {
-    double s = 0.0;
-    for (int i = 0; i < N; ++i) {
-      if (i == a) continue;
-      D[a][i] = (bw[i] / bw[a]) / (c->xi[a] - c->xi[i]);
-      s += D[a][i];
-    }
-    D[a][a] = -s;
-  }
-  for (int i = 0; i < N; ++i) {
-    double lm = 1.0, lp = 1.0;
-    for (int m = 0; m < N; ++m) {
-      if (m == i) continue;
-      lm *= (-1.0 - c->xi[m]) / (c->xi[i] - c->xi[m]);
-      lp *= (1.0 - c->xi[m]) / (c->xi[i] - c->xi[m]);
-    }
-    t.lm[i] = lm;
-    t.lp[i] = lp;
-    t.liftm[i] = lm / c->w[i];
-    t.liftp[i] = lp / c->w[i];
-    t.w[i] = c->w[i];
-    for (int a = 0; a < N; ++a) t.Dh[i * N + a] = c->w[a] * D[a][i] / c->w[i];
-  }
-  for (int i = 0; i < N; ++i) {
-    double s = 0.0;
-    for (int a = 0; a < N; ++a) {
-      s += t.Dh[i * N + a];
-      t.Dh32[i * N + a] = (float)t.Dh[i * N + a];
-    }
-    t.rs[i] = s;
-    t.lm32[i] = (float)t.lm[i];
-    t.lp32[i] = (float)t.lp[i];
-  }
-  const double h[3] = {c->L[0] / c->nx, c->L[1] / c->ny, c->L[2] / c->nz};
-  for (int d = 0; d < 3; ++d) {
-    t.sc[d] = 2.0 / h[d];
-    t.hinv[d] = 1.0 / h[d];
-  }
-  t.J = h[0] * h[1] * h[2] / 8.0;
-  t.gamma = c->gamma;
-  t.gm1 = c->gamma - 1.0;
-  t.nx = c->nx;
-  t.ny = c->ny;
-  t.nz = c->nz;
-  t.E = (int)c->E;
+  dg_build_tables(c->nx, c->ny, c->nz, c->p, c->gamma, c->L, &c->tab, c->xi, c->w);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -260,6 +202,81 @@ int check_state_pair(dg_ctx* c, const void* a, const char* an, const void* b, co
 }
 
 }  // namespace
+
+void dg_build_tables(int nx, int ny, int nz, int p, double gamma, const double L[3], DGTables* tp, double* xi,
+                     double* w) {
+  const int N = p + 1;
+  DGTables& t = *tp;
+  std::memset(&t, 0, sizeof(t));
+  gauss_legendre(N, xi, w);
+  // barycentric weights 1 / prod_{m != i} (xi_i - xi_m)
+  double bw[DG_MAXN];
+  for (int i = 0; i < N; ++i) {
+    double prod = 1.0;
+    for (int m = 0; m < N; ++m)
+      if (m != i) prod *= (xi[i] - xi[m]);
+    bw[i] = 1.0 / prod;
+  }
+  // D[a][i] = l_i'(xi_a): off-diagonal (bw_i / bw_a) / (xi_a - xi_i),
+  // diagonal from the zero row sum (derivative of a constant).
+  double D[DG_MAXN][DG_MAXN];
+  for (int a = 0; a < N; ++a) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) {
+      if (i == a) continue;
+      D[a][i] = (bw[i] / bw[a]) / (xi[a] - xi[i]);
+      s += D[a][i];
+    }
+    D[a][a] = -s;
+  }
+  for (int i = 0; i < N; ++i) {
+    double lm = 1.0, lp = 1.0;
+    for (int m = 0; m < N; ++m) {
+      if (m == i) continue;
+      lm *= (-1.0 - xi[m]) / (xi[i] - xi[m]);
+      lp *= (1.0 - xi[m]) / (xi[i] - xi[m]);
+    }
+    t.lm[i] = lm;
+    t.lp[i] = lp;
+    t.liftm[i] = lm / w[i];
+    t.liftp[i] = lp / w[i];
+    t.w[i] = w[i];
+    for (int a = 0; a < N; ++a) t.Dh[i * N + a] = w[a] * D[a][i] / w[i];
+  }
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int a = 0; a < N; ++a) {
+      s += t.Dh[i * N + a];
+      t.Dh32[i * N + a] = (float)t.Dh[i * N + a];
+    }
+    t.rs[i] = s;
+    t.lm32[i] = (float)t.lm[i];
+    t.lp32[i] = (float)t.lp[i];
+  }
+  const double h[3] = {L[0] / nx, L[1] / ny, L[2] / nz};
+  for (int d = 0; d < 3; ++d) {
+    t.sc[d] = 2.0 / h[d];
+    t.hinv[d] = 1.0 / h[d];
+  }
+  t.J = h[0] * h[1] * h[2] / 8.0;
+  t.gamma = gamma;
+  t.gm1 = gamma - 1.0;
+  t.nx = nx;
+  t.ny = ny;
+  t.nz = nz;
+  t.E = nx * ny * nz;
+}
+
+const double kDgRKA[5] = {kRKA[0], kRKA[1], kRKA[2], kRKA[3], kRKA[4]};
+const double kDgRKB[5] = {kRKB[0], kRKB[1], kRKB[2], kRKB[3], kRKB[4]};
+
+int dg_set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
 
 DGWorkspace dg_workspace_layout(const dg_ctx* c) {
   DGWorkspace L;

@@ -1,0 +1,36 @@
+// Internal declarations of the batched multi-mesh path.
+#pragma once
+
+#include "dg_internal.h"
+
+// Per-mesh record in device memory.
+struct DGBatchInst {
+  DGTables tab;      // tables and mesh sizes of this mesh
+  int N;             // p + 1
+  int epb;           // elements per workgroup (tile) for this mesh's degree
+  int64_t qoff;      // offset (doubles) of the mesh's block in Q / res / R
+  int64_t toff;      // offset (bytes) of the mesh's block in each trace set
+  double dt;         // time step of this mesh
+};
+
+struct DGBatchLaunch {
+  const DGBatchInst* inst;
+  const int2* items;  // (mesh, first element)
+  int nitems;
+  unsigned grid;
+  hipStream_t stream;
+  int f32;
+};
+
+int dg_batch_tile_list(int N, int* out, int max);
+int dg_batch_launch_trace(const DGBatchLaunch& L, const double* Q, char* T);
+int dg_batch_launch_stage(const DGBatchLaunch& L, int mode, double* Q, double* RR, const char* Tin, char* Tout,
+                          double a, double b, int first);
+int dg_batch_blocks_per_cu(int f32);
+
+// Shared with the single-mesh host code.
+void dg_build_tables(int nx, int ny, int nz, int p, double gamma, const double L[3], DGTables* t, double* xi,
+                     double* w);
+extern const double kDgRKA[5];
+extern const double kDgRKB[5];
+int dg_set_error(int code, const char* fmt, ...);

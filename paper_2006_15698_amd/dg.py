@@ -64,6 +64,19 @@ _SIGS = {
     "dg_integrals": (_i, [_vp, _vp, _dp]),
     "dg_max_wavespeed": (_i, [_vp, _vp, _dp]),
     "dg_check_state": (_i, [_vp, _vp]),
+    "dg_batch_create": (_vp, [_i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp, _d]),
+    "dg_batch_destroy": (None, [_vp]),
+    "dg_batch_set_stream": (_i, [_vp, _vp]),
+    "dg_batch_set_precision": (_i, [_vp, _i]),
+    "dg_batch_set_tile": (_i, [_vp, _i, _i]),
+    "dg_batch_tile_options": (_i, [_i, ctypes.POINTER(ctypes.c_int), _i]),
+    "dg_batch_offset": (_i64, [_vp, _i]),
+    "dg_batch_workspace_bytes": (_sz, [_vp]),
+    "dg_batch_set_workspace": (_i, [_vp, _vp, _sz]),
+    "dg_batch_set_dt": (_i, [_vp, _dp]),
+    "dg_batch_rhs": (_i, [_vp, _vp, _vp]),
+    "dg_batch_rk_steps": (_i, [_vp, _vp, _vp, _i]),
+    "dg_batch_graph_steps": (_i, [_vp, _vp, _vp, _i]),
     "dg_set_timing": (_i, [_vp, _i]),
     "dg_timing_read": (_i, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -234,6 +247,142 @@ def dg_timing_read(ctx):
     cnt = (ctypes.c_int64 * 5)()
     _check(_lib.dg_timing_read(ctx, ms, cnt))
     return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_KINDS)}
+
+
+# ---- batched meshes ----------------------------------------------------------
+def dg_batch_create(n, p, L, gamma=1.4):
+    """n: list of (nx, ny, nz); p: list of degrees; L: list of (Lx, Ly, Lz)."""
+    count = len(p)
+    na = (ctypes.c_int * (3 * count))(*[int(v) for t in n for v in t])
+    pa = (ctypes.c_int * count)(*[int(v) for v in p])
+    La = (ctypes.c_double * (3 * count))(*[float(v) for t in L for v in t])
+    b = _lib.dg_batch_create(count, na, pa, La, float(gamma))
+    if not b:
+        raise DGError(DG_EINVAL, dg_last_error())
+    return b
+
+
+def dg_batch_destroy(b):
+    _lib.dg_batch_destroy(b)
+
+
+def dg_batch_set_stream(b, stream=None):
+    return _check(_lib.dg_batch_set_stream(b, _stream_ptr(stream)))
+
+
+def dg_batch_set_precision(b, mode):
+    return _check(_lib.dg_batch_set_precision(b, int(mode)))
+
+
+def dg_batch_set_tile(b, p, epb):
+    return _check(_lib.dg_batch_set_tile(b, int(p), int(epb)))
+
+
+def dg_batch_tile_options(p):
+    out = (ctypes.c_int * 16)()
+    k = _lib.dg_batch_tile_options(int(p), out, 16)
+    return [out[i] for i in range(k)]
+
+
+def dg_batch_offset(b, i):
+    return int(_lib.dg_batch_offset(b, int(i)))
+
+
+def dg_batch_workspace_bytes(b):
+    return int(_lib.dg_batch_workspace_bytes(b))
+
+
+def dg_batch_set_workspace(b, ws, nbytes=None):
+    if nbytes is None:
+        nbytes = ws.numel() * ws.element_size()
+    return _check(_lib.dg_batch_set_workspace(b, _ptr(ws), int(nbytes)))
+
+
+def dg_batch_set_dt(b, dt):
+    arr = (ctypes.c_double * len(dt))(*[float(v) for v in dt])
+    return _check(_lib.dg_batch_set_dt(b, arr))
+
+
+def dg_batch_rhs(b, Q, R):
+    return _check(_lib.dg_batch_rhs(b, _ptr(Q), _ptr(R)))
+
+
+def dg_batch_rk_steps(b, Q, res, nsteps):
+    return _check(_lib.dg_batch_rk_steps(b, _ptr(Q), _ptr(res), int(nsteps)))
+
+
+def dg_batch_graph_steps(b, Q, res, nsteps):
+    return _check(_lib.dg_batch_graph_steps(b, _ptr(Q), _ptr(res), int(nsteps)))
+
+
+class Batch:
+    """Independent periodic meshes advanced together on one GPU.  State is
+    one flat float64 tensor; ``view(Q, i)`` is mesh i's block shaped
+    [5, nz, ny, nx, N, N, N]."""
+
+    def __init__(self, n, p, L, gamma=1.4, precision=DG_FP64, tiles=None, device=None):
+        self.n = [tuple(int(v) for v in t) for t in n]
+        self.p = [int(v) for v in p]
+        self.L = [tuple(float(v) for v in t) for t in L]
+        self.count = len(self.p)
+        self.device = torch.device(device or "cuda")
+        self.b = dg_batch_create(self.n, self.p, self.L, gamma)
+        dg_batch_set_precision(self.b, precision)
+        if tiles is None:
+            from .tune import load_tiles
+            tiles = load_tiles() or {}
+        self.tiles = dict(tiles)
+        for deg, epb in tiles.items():
+            dg_batch_set_tile(self.b, deg, epb)
+        self.offsets = [dg_batch_offset(self.b, i) for i in range(self.count + 1)]
+        nbytes = dg_batch_workspace_bytes(self.b)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        _check(_lib.dg_batch_set_workspace(self.b, aligned, nbytes))
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b:
+            dg_batch_destroy(b)
+            self.b = None
+
+    @property
+    def total(self):
+        return self.offsets[-1]
+
+    def empty(self):
+        return torch.empty(self.total, dtype=torch.float64, device=self.device)
+
+    def view(self, Q, i):
+        nx, ny, nz = self.n[i]
+        N = self.p[i] + 1
+        return Q[self.offsets[i]:self.offsets[i + 1]].view(5, nz, ny, nx, N, N, N)
+
+    def pack(self, states):
+        Q = self.empty()
+        for i, st in enumerate(states):
+            self.view(Q, i).copy_(st if isinstance(st, torch.Tensor) else torch.from_numpy(st))
+        return Q
+
+    def _s(self):
+        dg_batch_set_stream(self.b, None)
+
+    def set_dt(self, dt):
+        self._s()
+        dg_batch_set_dt(self.b, dt)
+
+    def rhs(self, Q, out=None):
+        out = self.empty() if out is None else out
+        self._s()
+        dg_batch_rhs(self.b, Q, out)
+        return out
+
+    def step(self, Q, res, nsteps=1, graph=False):
+        self._s()
+        if graph:
+            dg_batch_graph_steps(self.b, Q, res, nsteps)
+        else:
+            dg_batch_rk_steps(self.b, Q, res, nsteps)
 
 
 # ---- convenience -----------------------------------------------------------

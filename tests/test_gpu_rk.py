@@ -176,3 +176,24 @@ def test_conservation_over_steps(dgm):
     I1 = s.integrals(Qd)
     scale = np.array([I0[0], I0[0], I0[0], I0[0], I0[4]])
     assert np.all(np.abs(I1[:5] - I0[:5]) <= 1e-13 * scale)
+
+
+def test_tgv_c2_full_run_drift(dgm):
+    """Second workload as configured: 100 steps at CFL 0.3.  Mass (and
+    momentum, energy) are conserved to roundoff; the kinetic energy of the
+    inviscid flow changes only by the scheme's small dissipation at this
+    early time (t ~ 0.025)."""
+    import torch
+    L = (2 * math.pi,) * 3
+    s = dgm.Solver((32, 32, 32), 3, L=L)
+    Q = _dev(W.tgv(32, 3))
+    r = torch.zeros_like(Q)
+    dt = s.dt_cfl(Q, 0.3)
+    I0 = s.integrals(Q)
+    s.step(Q, r, dt, nsteps=100)
+    I1 = s.integrals(Q)
+    print("t_end", 100 * dt, "mass drift", (I1[0] - I0[0]) / I0[0], "KE drift", (I1[5] - I0[5]) / I0[5])
+    assert abs(I1[0] - I0[0]) <= 1e-13 * I0[0]
+    assert abs(I1[4] - I0[4]) <= 1e-13 * I0[4]
+    assert abs(I1[5] - I0[5]) <= 1e-5 * I0[5]
+    assert s.check_state(Q)
