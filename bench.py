@@ -52,9 +52,11 @@ def flops_per_dof_stage(N):
 
 
 def kernel_source_hash():
+    """Hash of every kernel source: counters taken on other sources are stale."""
     h = hashlib.sha256()
-    for f in ("kern_fp64.hip", "dg_internal.h"):
-        with open(os.path.join(ROOT, "paper_2006_15698_amd", "csrc", f), "rb") as fh:
+    d = os.path.join(ROOT, "paper_2006_15698_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -179,6 +181,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--exchange", default="neighbour", choices=["neighbour", "traces"],
+                    help="how a stage obtains its neighbours' face traces (FP64 path)")
+    ap.add_argument("--no-xcd-remap", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="instead of the solver, time a plain device-to-device copy of MIB MiB "
+                         "(calibrates HBM byte counters; reports the copy bandwidth)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -192,6 +200,26 @@ def main():
     import workloads as W
     from paper_2006_15698_amd import dg
 
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
+                          "ms_per_copy": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}))
+        return
+
     if args.workload == "batch512":
         print(json.dumps(run_batch(args)), flush=True)
         return
@@ -202,6 +230,9 @@ def main():
     L = (2 * math.pi,) * 3
     prec = dg.DG_FP64 if args.precision == "fp64" else dg.DG_FP32_MFMA
     s = dg.Solver((n, n, n), p, L=L, precision=prec)
+    s.set_option(dg.DG_OPT_EXCHANGE, dg.DG_EXCHANGE_NEIGHBOUR if args.exchange == "neighbour"
+                 else dg.DG_EXCHANGE_TRACES)
+    s.set_option(dg.DG_OPT_XCD_REMAP, 0 if args.no_xcd_remap else 1)
     dof = s.num_dof
     Q0 = torch.from_numpy(W.tgv(n, p)).cuda()
     dt = s.dt_cfl(Q0, 0.3)
@@ -233,7 +264,9 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32 contractions, f64 state",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "elements": n ** 3, "p": p,
-                   "dof": dof, "precision": args.precision, "dt": dt},
+                   "dof": dof, "precision": args.precision, "dt": dt,
+                   "exchange": args.exchange if args.precision == "fp64" else "traces",
+                   "xcd_remap": not args.no_xcd_remap},
     }
 
     if not args.no_roofline:
@@ -251,7 +284,9 @@ def main():
         traffic = measured_traffic(args.workload, args.precision)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": "k_stage (fused RHS + LSERK45 stage)",
+                           "kernel": ("k_stage_nb" if (args.exchange == "neighbour" and args.precision == "fp64")
+                                      else "k_stage32" if args.precision == "fp32" else "k_stage")
+                           + " (fused RHS + LSERK45 stage)",
                            "avg_launch_us": avg_s * 1e6, "launches": st_n,
                            "alg_bytes_per_launch": alg_bytes}
         fl = flops_per_dof_stage(p + 1) * dof

@@ -91,6 +91,22 @@ int dg_set_stream(dg_ctx* ctx, void* hip_stream);
  * DG_EUNSUPPORTED if the mode is not available for this p. */
 int dg_set_precision(dg_ctx* ctx, int mode);
 
+/* Tuning options (dg_set_option).
+ * DG_OPT_EXCHANGE: how an FP64 stage obtains its neighbours' face traces.
+ *   DG_EXCHANGE_NEIGHBOUR (default): interpolated in the launch itself from
+ *   the neighbour elements' state (read through the caches); the state is
+ *   ping-ponged between the caller's Q and a workspace buffer, so a call
+ *   with an odd number of stages ends with one device-to-device copy.
+ *   DG_EXCHANGE_TRACES: every launch writes the face traces of its updated
+ *   state to a workspace buffer that the next launch reads.
+ *   Both give bitwise identical results.
+ * DG_OPT_XCD_REMAP: 1 (default) maps workgroups to element blocks so that
+ *   each XCD of the MI355X processes a contiguous range of elements
+ *   (neighbour path); 0 uses the launch order. */
+enum { DG_OPT_EXCHANGE = 1, DG_OPT_XCD_REMAP = 2 };
+enum { DG_EXCHANGE_TRACES = 0, DG_EXCHANGE_NEIGHBOUR = 1 };
+int dg_set_option(dg_ctx* ctx, int key, int value);
+
 /* Bytes of device workspace that the compute calls need (face-trace
  * ping-pong buffers and reduction partials).  Depends on the mesh and p. */
 size_t dg_workspace_bytes(const dg_ctx* ctx);

@@ -19,7 +19,10 @@ LIB = os.path.join(HERE, "libdg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# -ffp-contract=on: multiply-adds are fused only inside one source
+# expression (a fixed rule), never across statements, so every kernel that
+# shares a device function rounds identically however it was inlined.
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result"]

@@ -174,10 +174,32 @@ int run_reduce(dg_ctx* c, const double* Q, double out[DG_RED_VALS]) {
   return DG_OK;
 }
 
+double* q2_buf(dg_ctx* c) { return (double*)(c->ws + dg_workspace_layout(c).off_q2); }
+
+// Neighbour-read sequencing: stage g reads buf[g % 2] and writes
+// buf[(g + 1) % 2] with buf = {Q, Q2}; an odd count ends in Q2, copied back.
+int stages_nb(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
+  double* buf[2] = {Q, q2_buf(c)};
+  int err = 0;
+  for (int g = 0; g < count; ++g) {
+    const int s = (s0 + g) % 5;
+    err = timed(c, TK_STAGE, [&] {
+      return dg_launch_stage_nb(c, buf[g & 1], buf[(g + 1) & 1], res, 1, kRKA[s], kRKB[s], dt, s == 0);
+    });
+    if (err) return hip_fail(err, "stage launch");
+  }
+  if (count & 1) {
+    err = (int)hipMemcpyAsync(Q, buf[1], state_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    if (err) return hip_fail(err, "state copy");
+  }
+  return DG_OK;
+}
+
 int stages(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
   // Traces of the initial Q, then `count` stages starting at stage s0; each
   // stage but the last writes the traces of its updated Q for the next.
   const bool f32 = c->precision == DG_FP32_MFMA;
+  if (!f32 && c->exchange == DG_EXCHANGE_NEIGHBOUR) return stages_nb(c, Q, res, dt, s0, count);
   int err = timed(c, TK_TRACE, [&] {
     return f32 ? dg_launch_trace_f32(c, Q, (char*)trace_buf(c, 0)) : dg_launch_trace(c, Q, trace_buf(c, 0));
   });
@@ -290,7 +312,8 @@ DGWorkspace dg_workspace_layout(const dg_ctx* c) {
   L.off_vjp = L.off_red + red_bytes;
   // adjoint scratch for the reverse RK stage: two state-sized buffers
   const size_t vjp_bytes = 2 * align256(DG_NF * N3 * (size_t)c->E * sizeof(double));
-  L.total = L.off_vjp + vjp_bytes;
+  L.off_q2 = L.off_vjp + vjp_bytes;
+  L.total = L.off_q2 + align256(DG_NF * N3 * (size_t)c->E * sizeof(double));
   return L;
 }
 
@@ -332,6 +355,8 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
   c->L[0] = c->L[1] = c->L[2] = 1.0;
   c->stream = nullptr;
   c->precision = DG_FP64;
+  c->exchange = DG_EXCHANGE_NEIGHBOUR;
+  c->xcd_remap = 1;
   build_tables(c);
   g_err[0] = 0;
   return c;
@@ -406,6 +431,21 @@ int dg_set_precision(dg_ctx* c, int mode) {
   return fail(DG_EINVAL, "unknown precision mode %d", mode);
 }
 
+int dg_set_option(dg_ctx* c, int key, int value) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (key == DG_OPT_EXCHANGE) {
+    if (value != DG_EXCHANGE_TRACES && value != DG_EXCHANGE_NEIGHBOUR)
+      return fail(DG_EINVAL, "unknown exchange %d", value);
+    c->exchange = value;
+    return DG_OK;
+  }
+  if (key == DG_OPT_XCD_REMAP) {
+    c->xcd_remap = value ? 1 : 0;
+    return DG_OK;
+  }
+  return fail(DG_EINVAL, "unknown option %d", key);
+}
+
 size_t dg_workspace_bytes(const dg_ctx* c) {
   if (!c) return 0;
   return dg_workspace_layout(c).total;
@@ -440,6 +480,11 @@ int dg_rhs(dg_ctx* c, const double* Q, double* R) {
   rc = check_state_pair(c, Q, "Q", R, "R");
   if (rc) return rc;
   const bool f32 = c->precision == DG_FP32_MFMA;
+  if (!f32 && c->exchange == DG_EXCHANGE_NEIGHBOUR) {
+    int err = timed(c, TK_RHS, [&] { return dg_launch_stage_nb(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0); });
+    if (err) return hip_fail(err, "rhs launch");
+    return DG_OK;
+  }
   int err = timed(c, TK_TRACE, [&] {
     return f32 ? dg_launch_trace_f32(c, Q, (char*)trace_buf(c, 0)) : dg_launch_trace(c, Q, trace_buf(c, 0));
   });

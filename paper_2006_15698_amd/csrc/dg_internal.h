@@ -47,6 +47,8 @@ struct dg_ctx {
   DGTables tab;
   int timing_on;
   void* timing;   // DGTiming*, owned, created by dg_set_timing
+  int exchange;   // DG_EXCHANGE_TRACES or DG_EXCHANGE_NEIGHBOUR (FP64 path)
+  int xcd_remap;  // XCD-aware workgroup -> block mapping (neighbour path)
 };
 
 // Workspace carve-up (byte offsets, each 256-aligned).
@@ -55,6 +57,7 @@ struct DGWorkspace {
   size_t off_trace0, off_trace1;
   size_t off_red;       // reduction partials
   size_t off_vjp;       // adjoint scratch: two state-sized buffers
+  size_t off_q2;        // second state buffer of the neighbour-read path
   size_t total;
 };
 DGWorkspace dg_workspace_layout(const dg_ctx* c);
@@ -73,6 +76,10 @@ int dg_launch_rhs(const dg_ctx* c, const double* Q, const double* Tin, double* R
 // Tout != nullptr.
 int dg_launch_stage(const dg_ctx* c, double* Q, double* res, const double* Tin,
                     double* Tout, double a, double b, double dt, int first);
+// Neighbour-read stage: Qin -> Qout; mode 0 writes RR = dQ/dt, mode 1 the
+// RK update (res = RR in place).
+int dg_launch_stage_nb(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
+                       double dt, int first);
 // Reductions: per-block partials then a fixed-order final pass into
 // red[DG_RED_BLOCKS*DG_RED_VALS .. +DG_RED_VALS).
 int dg_launch_reduce(const dg_ctx* c, const double* Q, double* red);

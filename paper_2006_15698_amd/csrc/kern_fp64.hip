@@ -10,6 +10,7 @@
 
 #include "dg_internal.h"
 #include "stage_fp64.h"
+#include "stage_nb.h"
 
 namespace {
 
@@ -41,6 +42,18 @@ k_stage(DGTables tb, double* __restrict__ Q, double* __restrict__ RR,
   constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
   __shared__ double smem[dgdev::Fp64Smem<N, EPB>::size];
   dgdev::stage_body<N, MODE, EPB, NT>(tb, Q, RR, Tin, Tout, rka, rkb, dt, first, blockIdx.x * EPB, smem, threadIdx.x);
+}
+
+// Neighbour-read variant: Qin -> Qout (different buffers), no trace buffers.
+// remap != 0: XCD-aware workgroup -> block mapping.
+template <int N, int MODE>
+__global__ void __launch_bounds__(Cfg<N>::NT)
+k_stage_nb(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,
+           double rka, double rkb, double dt, int first, int remap) {
+  constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
+  __shared__ double smem[dgdev::Fp64Smem<N, EPB>::size];
+  const int blk = remap ? dgdev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  dgdev::stage_nb_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, blk * EPB, smem, threadIdx.x);
 }
 
 // ---- reductions -----------------------------------------------------------
@@ -150,6 +163,20 @@ int launch_stage_n(const dg_ctx* c, double* Q, double* RR, const double* Tin, do
 }
 
 template <int N>
+int launch_stage_nb_n(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
+                      double dt, int first) {
+  constexpr int EPB = Cfg<N>::EPB;
+  const unsigned grid = (unsigned)((c->E + EPB - 1) / EPB);
+  const dim3 blk(Cfg<N>::NT);
+  const int remap = c->xcd_remap;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_stage_nb<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, remap);
+  else
+    hipLaunchKernelGGL((k_stage_nb<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, remap);
+  return (int)hipGetLastError();
+}
+
+template <int N>
 int launch_reduce_n(const dg_ctx* c, const double* Q, double* red) {
   hipLaunchKernelGGL(k_reduce_partial<N>, dim3(DG_RED_BLOCKS), dim3(RED_NT), 0, c->stream, c->tab, Q, red);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_NT), 0, c->stream, red);
@@ -187,6 +214,13 @@ int dg_launch_stage(const dg_ctx* c, double* Q, double* res, const double* Tin, 
                     double a, double b, double dt, int first) {
   const int mode = Tout ? 2 : 1;
 #define CALL(n) launch_stage_n<n>(c, Q, res, Tin, Tout, mode, a, b, dt, first)
+  DG_DISPATCH_N(c->N, CALL)
+#undef CALL
+}
+
+int dg_launch_stage_nb(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
+                       double dt, int first) {
+#define CALL(n) launch_stage_nb_n<n>(c, Qin, Qout, RR, mode, a, b, dt, first)
   DG_DISPATCH_N(c->N, CALL)
 #undef CALL
 }

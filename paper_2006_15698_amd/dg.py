@@ -36,6 +36,10 @@ DG_ENONPHYSICAL = -5
 DG_EWORKSPACE = -6
 DG_FP64 = 0
 DG_FP32_MFMA = 1
+DG_OPT_EXCHANGE = 1
+DG_OPT_XCD_REMAP = 2
+DG_EXCHANGE_TRACES = 0
+DG_EXCHANGE_NEIGHBOUR = 1
 
 ERROR_NAMES = {DG_EINVAL: "DG_EINVAL", DG_EUNSUPPORTED: "DG_EUNSUPPORTED", DG_EHIP: "DG_EHIP",
                DG_EALIAS: "DG_EALIAS", DG_ENONPHYSICAL: "DG_ENONPHYSICAL",
@@ -77,6 +81,7 @@ _SIGS = {
     "dg_batch_rhs": (_i, [_vp, _vp, _vp]),
     "dg_batch_rk_steps": (_i, [_vp, _vp, _vp, _i]),
     "dg_batch_graph_steps": (_i, [_vp, _vp, _vp, _i]),
+    "dg_set_option": (_i, [_vp, _i, _i]),
     "dg_set_timing": (_i, [_vp, _i]),
     "dg_timing_read": (_i, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -155,6 +160,10 @@ def dg_set_stream(ctx, stream=None):
 
 def dg_set_precision(ctx, mode):
     return _check(_lib.dg_set_precision(ctx, int(mode)))
+
+
+def dg_set_option(ctx, key, value):
+    return _check(_lib.dg_set_option(ctx, int(key), int(value)))
 
 
 def dg_workspace_bytes(ctx):
@@ -426,6 +435,9 @@ class Solver:
 
     def set_precision(self, mode):
         dg_set_precision(self.ctx, mode)
+
+    def set_option(self, key, value):
+        dg_set_option(self.ctx, key, value)
 
     def _s(self):
         dg_set_stream(self.ctx, None)
