@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--exchange", default="neighbour", choices=["neighbour", "traces"],
                     help="how a stage obtains its neighbours' face traces (FP64 path)")
-    ap.add_argument("--no-xcd-remap", action="store_true")
+    ap.add_argument("--xcd-remap", action="store_true", help="XCD-aware workgroup mapping (default off)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, time a plain device-to-device copy of MIB MiB "
                          "(calibrates HBM byte counters; reports the copy bandwidth)")
@@ -232,7 +232,7 @@ def main():
     s = dg.Solver((n, n, n), p, L=L, precision=prec)
     s.set_option(dg.DG_OPT_EXCHANGE, dg.DG_EXCHANGE_NEIGHBOUR if args.exchange == "neighbour"
                  else dg.DG_EXCHANGE_TRACES)
-    s.set_option(dg.DG_OPT_XCD_REMAP, 0 if args.no_xcd_remap else 1)
+    s.set_option(dg.DG_OPT_XCD_REMAP, 1 if args.xcd_remap else 0)
     dof = s.num_dof
     Q0 = torch.from_numpy(W.tgv(n, p)).cuda()
     dt = s.dt_cfl(Q0, 0.3)
@@ -266,7 +266,7 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "elements": n ** 3, "p": p,
                    "dof": dof, "precision": args.precision, "dt": dt,
                    "exchange": args.exchange if args.precision == "fp64" else "traces",
-                   "xcd_remap": not args.no_xcd_remap},
+                   "xcd_remap": bool(args.xcd_remap)},
     }
 
     if not args.no_roofline:

@@ -100,9 +100,9 @@ int dg_set_precision(dg_ctx* ctx, int mode);
  *   DG_EXCHANGE_TRACES: every launch writes the face traces of its updated
  *   state to a workspace buffer that the next launch reads.
  *   Both give bitwise identical results.
- * DG_OPT_XCD_REMAP: 1 (default) maps workgroups to element blocks so that
- *   each XCD of the MI355X processes a contiguous range of elements
- *   (neighbour path); 0 uses the launch order. */
+ * DG_OPT_XCD_REMAP: 1 maps workgroups to element blocks so that each XCD
+ *   of the MI355X processes a contiguous range of elements (neighbour
+ *   path); 0 (default, measured faster) uses the launch order. */
 enum { DG_OPT_EXCHANGE = 1, DG_OPT_XCD_REMAP = 2 };
 enum { DG_EXCHANGE_TRACES = 0, DG_EXCHANGE_NEIGHBOUR = 1 };
 int dg_set_option(dg_ctx* ctx, int key, int value);
@@ -213,8 +213,9 @@ int dg_batch_set_workspace(dg_batch* b, void* dptr, size_t bytes);
 int dg_batch_set_dt(dg_batch* b, const double* dt);
 /* R = dQ/dt of every mesh. */
 int dg_batch_rhs(dg_batch* b, const double* Q, double* R);
-/* nsteps LSERK45 steps of every mesh with its own dt: one trace launch,
- * then one persistent launch per stage. */
+/* nsteps LSERK45 steps of every mesh with its own dt: one persistent
+ * launch per stage; the state alternates between Q and a workspace buffer
+ * (an odd nsteps ends with one device-to-device copy back into Q). */
 int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps);
 /* Same result as dg_batch_rk_steps, with the five stage launches of a step
  * replayed from HIP graphs (captured on first use for this (Q, res) pair and

@@ -22,7 +22,6 @@ struct dg_batch {
   std::vector<int64_t> qoff;       // count + 1
   int epb_for_N[DG_MAXN + 1] = {0};
   std::vector<int2> items;
-  size_t trace_set_bytes = 0;
   hipStream_t stream = nullptr;
   int precision = DG_FP64;
   char* ws = nullptr;
@@ -41,16 +40,17 @@ struct dg_batch {
 namespace {
 
 struct Layout {
-  size_t off_inst, off_items, off_t0, off_t1, total;
+  size_t off_inst, off_items, off_q2, total;
 };
 
+// Workspace: per-mesh records, the work list, and the second state buffer of
+// the Q ping-pong (as long as the whole batch state).
 Layout layout(const dg_batch* b) {
   Layout L;
   L.off_inst = 0;
   L.off_items = al256(sizeof(DGBatchInst) * b->count);
-  L.off_t0 = L.off_items + al256(sizeof(int2) * b->items.size());
-  L.off_t1 = L.off_t0 + al256(b->trace_set_bytes);
-  L.total = L.off_t1 + al256(b->trace_set_bytes);
+  L.off_q2 = L.off_items + al256(sizeof(int2) * b->items.size());
+  L.total = L.off_q2 + al256((size_t)b->qoff[b->count] * sizeof(double));
   return L;
 }
 
@@ -95,14 +95,16 @@ int hipfail(int err, const char* what) {
   return dg_set_error(DG_EHIP, "%s: HIP error %d (%s)", what, err, hipGetErrorString((hipError_t)err));
 }
 
-// Launch the five stages of one step with the given trace parity on stream s.
+double* q2_of(const dg_batch* b) { return (double*)(b->ws + layout(b).off_q2); }
+
+// The five stage launches of one step on stream s.  parity 0: the step
+// starts from Q (and ends in Q2); parity 1: starts from Q2.
 int launch_step(dg_batch* b, hipStream_t s, int parity, double* Q, double* res) {
-  const Layout L = layout(b);
-  char* T[2] = {b->ws + L.off_t0, b->ws + L.off_t1};
+  double* buf[2] = {Q, q2_of(b)};
   const DGBatchLaunch l = launch_of(b, s);
   for (int st = 0; st < 5; ++st) {
     const int g = parity + st;
-    int err = dg_batch_launch_stage(l, 2, Q, res, T[g & 1], T[(g + 1) & 1], kDgRKA[st], kDgRKB[st], st == 0);
+    int err = dg_batch_launch_stage(l, 1, buf[g & 1], buf[(g + 1) & 1], res, kDgRKA[st], kDgRKB[st], st == 0);
     if (err) return err;
   }
   return 0;
@@ -136,7 +138,6 @@ dg_batch* dg_batch_create(int count, const int* n, const int* p, const double* L
     b->epb_for_N[N] = k ? opts[k - 1] : 0;   // default: the largest tile
   }
   int64_t q = 0;
-  size_t t = 0;
   for (int i = 0; i < count; ++i) {
     const int nx = n[3 * i], ny = n[3 * i + 1], nz = n[3 * i + 2];
     const int64_t E = (int64_t)nx * ny * nz;
@@ -165,12 +166,9 @@ dg_batch* dg_batch_create(int count, const int* n, const int* p, const double* L
     I.qoff = q;
     b->qoff[i] = q;
     q += 5 * E * N3;
-    I.toff = (int64_t)t;
-    t += al256((size_t)30 * I.N * I.N * (size_t)E * sizeof(double));
     I.dt = 0.0;
   }
   b->qoff[count] = q;
-  b->trace_set_bytes = t;
   build_items(b);
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) {
@@ -275,11 +273,8 @@ int dg_batch_rhs(dg_batch* b, const double* Q, double* R) {
   const size_t sb = (size_t)b->qoff[b->count] * sizeof(double);
   if ((const char*)Q < (const char*)R + sb && (const char*)R < (const char*)Q + sb)
     return dg_set_error(DG_EALIAS, "R overlaps Q");
-  const Layout L = layout(b);
   const DGBatchLaunch l = launch_of(b, b->stream);
-  int err = dg_batch_launch_trace(l, Q, b->ws + L.off_t0);
-  if (err) return hipfail(err, "batch trace launch");
-  err = dg_batch_launch_stage(l, 0, const_cast<double*>(Q), R, b->ws + L.off_t0, nullptr, 0.0, 0.0, 0);
+  int err = dg_batch_launch_stage(l, 0, Q, nullptr, R, 0.0, 0.0, 0);
   if (err) return hipfail(err, "batch rhs launch");
   return DG_OK;
 }
@@ -292,13 +287,14 @@ int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps) {
   const size_t sb = (size_t)b->qoff[b->count] * sizeof(double);
   if ((char*)Q < (char*)res + sb && (char*)res < (char*)Q + sb) return dg_set_error(DG_EALIAS, "res overlaps Q");
   if (nsteps == 0) return DG_OK;
-  const Layout L = layout(b);
-  const DGBatchLaunch l = launch_of(b, b->stream);
-  int err = dg_batch_launch_trace(l, Q, b->ws + L.off_t0);
-  if (err) return hipfail(err, "batch trace launch");
+  int err = 0;
   for (int n = 0; n < nsteps; ++n) {
-    err = launch_step(b, b->stream, (5 * n) & 1, Q, res);
+    err = launch_step(b, b->stream, n & 1, Q, res);
     if (err) return hipfail(err, "batch stage launch");
+  }
+  if (nsteps & 1) {
+    err = (int)hipMemcpyAsync(Q, q2_of(b), sb, hipMemcpyDeviceToDevice, b->stream);
+    if (err) return hipfail(err, "state copy");
   }
   return DG_OK;
 }
@@ -345,13 +341,13 @@ int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps) {
   b->gQ = Q;
   b->gR = res;
   b->gprec = b->precision;
-  const Layout L = layout(b);
-  const DGBatchLaunch l = launch_of(b, b->gstream);
-  err = dg_batch_launch_trace(l, Q, b->ws + L.off_t0);
-  if (err) return hipfail(err, "batch trace launch");
   for (int n = 0; n < nsteps; ++n) {
-    err = (int)hipGraphLaunch(b->gexec[(5 * n) & 1], b->gstream);
+    err = (int)hipGraphLaunch(b->gexec[n & 1], b->gstream);
     if (err) return hipfail(err, "graph launch");
+  }
+  if (nsteps & 1) {
+    err = (int)hipMemcpyAsync(Q, q2_of(b), sb, hipMemcpyDeviceToDevice, b->gstream);
+    if (err) return hipfail(err, "state copy");
   }
   err = (int)hipEventRecord(b->ev_out, b->gstream);
   if (err) return hipfail(err, "event record");

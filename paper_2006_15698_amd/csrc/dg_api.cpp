@@ -184,7 +184,9 @@ int stages_nb(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
   for (int g = 0; g < count; ++g) {
     const int s = (s0 + g) % 5;
     err = timed(c, TK_STAGE, [&] {
-      return dg_launch_stage_nb(c, buf[g & 1], buf[(g + 1) & 1], res, 1, kRKA[s], kRKB[s], dt, s == 0);
+      return c->precision == DG_FP32_MFMA
+                 ? dg_launch_stage_nb_f32(c, buf[g & 1], buf[(g + 1) & 1], res, 1, kRKA[s], kRKB[s], dt, s == 0)
+                 : dg_launch_stage_nb(c, buf[g & 1], buf[(g + 1) & 1], res, 1, kRKA[s], kRKB[s], dt, s == 0);
     });
     if (err) return hip_fail(err, "stage launch");
   }
@@ -199,7 +201,7 @@ int stages(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
   // Traces of the initial Q, then `count` stages starting at stage s0; each
   // stage but the last writes the traces of its updated Q for the next.
   const bool f32 = c->precision == DG_FP32_MFMA;
-  if (!f32 && c->exchange == DG_EXCHANGE_NEIGHBOUR) return stages_nb(c, Q, res, dt, s0, count);
+  if (c->exchange == DG_EXCHANGE_NEIGHBOUR) return stages_nb(c, Q, res, dt, s0, count);
   int err = timed(c, TK_TRACE, [&] {
     return f32 ? dg_launch_trace_f32(c, Q, (char*)trace_buf(c, 0)) : dg_launch_trace(c, Q, trace_buf(c, 0));
   });
@@ -356,7 +358,7 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
   c->stream = nullptr;
   c->precision = DG_FP64;
   c->exchange = DG_EXCHANGE_NEIGHBOUR;
-  c->xcd_remap = 1;
+  c->xcd_remap = 0;
   build_tables(c);
   g_err[0] = 0;
   return c;
@@ -480,8 +482,11 @@ int dg_rhs(dg_ctx* c, const double* Q, double* R) {
   rc = check_state_pair(c, Q, "Q", R, "R");
   if (rc) return rc;
   const bool f32 = c->precision == DG_FP32_MFMA;
-  if (!f32 && c->exchange == DG_EXCHANGE_NEIGHBOUR) {
-    int err = timed(c, TK_RHS, [&] { return dg_launch_stage_nb(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0); });
+  if (c->exchange == DG_EXCHANGE_NEIGHBOUR) {
+    int err = timed(c, TK_RHS, [&] {
+      return f32 ? dg_launch_stage_nb_f32(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0)
+                 : dg_launch_stage_nb(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0);
+    });
     if (err) return hip_fail(err, "rhs launch");
     return DG_OK;
   }

@@ -9,7 +9,6 @@ struct DGBatchInst {
   int N;             // p + 1
   int epb;           // elements per workgroup (tile) for this mesh's degree
   int64_t qoff;      // offset (doubles) of the mesh's block in Q / res / R
-  int64_t toff;      // offset (bytes) of the mesh's block in each trace set
   double dt;         // time step of this mesh
 };
 
@@ -23,9 +22,10 @@ struct DGBatchLaunch {
 };
 
 int dg_batch_tile_list(int N, int* out, int max);
-int dg_batch_launch_trace(const DGBatchLaunch& L, const double* Q, char* T);
-int dg_batch_launch_stage(const DGBatchLaunch& L, int mode, double* Q, double* RR, const char* Tin, char* Tout,
-                          double a, double b, int first);
+// mode 0: RR = dQ/dt of every mesh (Qout unused); mode 1: RK stage,
+// Qout = Qin + b res, res = RR in place.
+int dg_batch_launch_stage(const DGBatchLaunch& L, int mode, const double* Qin, double* Qout, double* RR, double a,
+                          double b, int first);
 int dg_batch_blocks_per_cu(int f32);
 
 // Shared with the single-mesh host code.

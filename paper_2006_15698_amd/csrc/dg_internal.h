@@ -98,3 +98,5 @@ int dg_launch_rhs_f32(const dg_ctx* c, const double* Q, const char* tin, double*
 int dg_launch_stage_f32(const dg_ctx* c, double* Q, double* res, const char* tin, char* tout, double a,
                         double b, double dt, int first);
 bool dg_f32_supported(int N);
+int dg_launch_stage_nb_f32(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a,
+                           double b, double dt, int first);

@@ -3,15 +3,17 @@
 //
 // A work list of (mesh, first element) items, one item per workgroup's worth
 // of elements, is walked by a persistent grid (static round robin: item k
-// belongs to block k mod gridDim).  Each item runs the same fused stage body
-// as the single-mesh kernel (stage_fp64.h / stage_fp32.h) with the
-// compile-time degree N and elements-per-workgroup EPB of its mesh, on a
-// shared-memory buffer sized for the largest (N, EPB) variant.  Every
-// variant uses 256 threads.
+// belongs to block k mod gridDim).  Each item runs the same fused
+// neighbour-read stage body as the single-mesh kernel (stage_nb.h /
+// stage_fp32.h) with the compile-time degree N and elements-per-workgroup
+// EPB of its mesh, on a shared-memory buffer sized for the largest (N, EPB)
+// variant.  Every variant uses 256 threads.  The state of all meshes
+// alternates between two buffers (Qin -> Qout) from launch to launch.
 
 #include "dg_batch.h"
 #include "stage_fp32.h"
 #include "stage_fp64.h"
+#include "stage_nb.h"
 
 namespace {
 
@@ -24,7 +26,7 @@ constexpr int BNT = 256;
 template <int N, int EPB>
 constexpr int smax64() { return dgdev::Fp64Smem<N, EPB>::size; }
 template <int N, int EPB>
-constexpr int smax32() { return dgdev::Fp32Smem<N, EPB>::bytes; }
+constexpr int smax32() { return dgdev::Nb32Smem<N, EPB>::bytes; }
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 #define DG_SZ64(n, e) smax64<n, e>(),
@@ -36,39 +38,20 @@ constexpr int kSmem64 = arrmax(kSizes64, sizeof(kSizes64) / sizeof(int));       
 constexpr int kSmem32 = (arrmax(kSizes32, sizeof(kSizes32) / sizeof(int)) + 7) / 8;  // doubles
 
 template <int MODE, bool F32>
-__device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, double* Q, double* RR, const char* Tin,
-                                         char* Tout, double a, double b, int first, double* smem, int tid) {
+__device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, const double* Qin, double* Qout, double* RR,
+                                         double a, double b, int first, double* smem, int tid) {
   // uniform across the workgroup: an SGPR value keeps the dispatch a scalar
   // branch (a divergent switch would overlap every variant's registers)
   const int key = __builtin_amdgcn_readfirstlane(I.N * 64 + I.epb);
-  double* q = Q + I.qoff;
+  const double* qi = Qin + I.qoff;
+  double* qo = Qout ? Qout + I.qoff : nullptr;
   double* rr = RR + I.qoff;
-  const char* ti = Tin + I.toff;
-  char* to = Tout ? Tout + I.toff : nullptr;
-#define DG_CASE(n, e)                                                                                         \
-  case n * 64 + e:                                                                                            \
-    if (F32)                                                                                                  \
-      dgdev::stage_body32<n, MODE, e, BNT>(I.tab, q, rr, ti, to, a, b, I.dt, first, e0, smem, tid);                \
-    else                                                                                                      \
-      dgdev::stage_body<n, MODE, e, BNT>(I.tab, q, rr, (const double*)ti, (double*)to, a, b, I.dt, first, e0, \
-                                         smem, tid);                                                          \
-    break;
-  switch (key) { DG_BATCH_VARIANTS(DG_CASE) default: break; }
-#undef DG_CASE
-}
-
-template <bool F32>
-__device__ __forceinline__ void run_trace_item(const DGBatchInst& I, int e0, const double* Q, char* T, double* smem,
-                                               int tid) {
-  const int key = __builtin_amdgcn_readfirstlane(I.N * 64 + I.epb);
-  const double* q = Q + I.qoff;
-  char* t = T + I.toff;
-#define DG_CASE(n, e)                                                     \
-  case n * 64 + e:                                                        \
-    if (F32)                                                              \
-      dgdev::trace_body32<n, e, BNT>(I.tab, q, t, e0, smem, tid);            \
-    else                                                                  \
-      dgdev::trace_body<n, e, BNT>(I.tab, q, (double*)t, e0, smem, tid);     \
+#define DG_CASE(n, e)                                                                                  \
+  case n * 64 + e:                                                                                     \
+    if (F32)                                                                                           \
+      dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, smem, tid);    \
+    else                                                                                               \
+      dgdev::stage_nb_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, smem, tid);      \
     break;
   switch (key) { DG_BATCH_VARIANTS(DG_CASE) default: break; }
 #undef DG_CASE
@@ -77,8 +60,8 @@ __device__ __forceinline__ void run_trace_item(const DGBatchInst& I, int e0, con
 template <int MODE, bool F32>
 __global__ void __launch_bounds__(BNT)
 k_batch_stage(const DGBatchInst* __restrict__ inst, const int2* __restrict__ items, int nitems,
-              double* __restrict__ Q, double* __restrict__ RR, const char* __restrict__ Tin,
-              char* __restrict__ Tout, double a, double b, int first) {
+              const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR, double a,
+              double b, int first) {
   __shared__ double smem[F32 ? kSmem32 : kSmem64];
   for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
     const int2 w = items[k];
@@ -90,23 +73,7 @@ k_batch_stage(const DGBatchInst* __restrict__ inst, const int2* __restrict__ ite
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     __syncthreads();  // the previous item's shared-memory reads are complete
-    run_item<MODE, F32>(inst[mi], e0, Q, RR, Tin, Tout, a, b, first, smem, tid);
-  }
-}
-
-template <bool F32>
-__global__ void __launch_bounds__(BNT)
-k_batch_trace(const DGBatchInst* __restrict__ inst, const int2* __restrict__ items, int nitems,
-              const double* __restrict__ Q, char* __restrict__ T) {
-  __shared__ double smem[F32 ? kSmem32 : kSmem64];
-  for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
-    const int2 w = items[k];
-    const int mi = __builtin_amdgcn_readfirstlane(w.x);
-    const int e0 = __builtin_amdgcn_readfirstlane(w.y);
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    __syncthreads();
-    run_trace_item<F32>(inst[mi], e0, Q, T, smem, tid);
+    run_item<MODE, F32>(inst[mi], e0, Qin, Qout, RR, a, b, first, smem, tid);
   }
 }
 
@@ -121,27 +88,17 @@ int dg_batch_tile_list(int N, int* out, int max) {
   return n;
 }
 
-int dg_batch_launch_trace(const DGBatchLaunch& L, const double* Q, char* T) {
-  if (L.f32)
-    hipLaunchKernelGGL(k_batch_trace<true>, dim3(L.grid), dim3(BNT), 0, L.stream, L.inst, L.items, L.nitems, Q, T);
-  else
-    hipLaunchKernelGGL(k_batch_trace<false>, dim3(L.grid), dim3(BNT), 0, L.stream, L.inst, L.items, L.nitems, Q, T);
-  return (int)hipGetLastError();
-}
-
-int dg_batch_launch_stage(const DGBatchLaunch& L, int mode, double* Q, double* RR, const char* Tin, char* Tout,
-                          double a, double b, int first) {
+int dg_batch_launch_stage(const DGBatchLaunch& L, int mode, const double* Qin, double* Qout, double* RR, double a,
+                          double b, int first) {
 #define DG_L(m, f)                                                                                           \
   hipLaunchKernelGGL((k_batch_stage<m, f>), dim3(L.grid), dim3(BNT), 0, L.stream, L.inst, L.items, L.nitems, \
-                     Q, RR, Tin, Tout, a, b, first)
+                     Qin, Qout, RR, a, b, first)
   if (L.f32) {
     if (mode == 0) DG_L(0, true);
-    else if (mode == 1) DG_L(1, true);
-    else DG_L(2, true);
+    else DG_L(1, true);
   } else {
     if (mode == 0) DG_L(0, false);
-    else if (mode == 1) DG_L(1, false);
-    else DG_L(2, false);
+    else DG_L(1, false);
   }
 #undef DG_L
   return (int)hipGetLastError();
@@ -149,8 +106,8 @@ int dg_batch_launch_stage(const DGBatchLaunch& L, int mode, double* Q, double* R
 
 int dg_batch_blocks_per_cu(int f32) {
   int nb = 0;
-  hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_stage<2, true>, BNT, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_stage<2, false>, BNT, 0);
+  hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_stage<1, true>, BNT, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_stage<1, false>, BNT, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

@@ -4,6 +4,7 @@
 
 #include "dg_internal.h"
 #include "stage_fp32.h"
+#include "stage_nb.h"
 
 namespace {
 
@@ -31,6 +32,31 @@ k_stage32(DGTables tb, double* __restrict__ Q, double* __restrict__ RR, const ch
   constexpr int EPB = FCfg<N>::EPB, NT = FCfg<N>::NT;
   __shared__ double smem[(dgdev::Fp32Smem<N, EPB>::bytes + 7) / 8];
   dgdev::stage_body32<N, MODE, EPB, NT>(tb, Q, RR, Tin, Tout, rka, rkb, dt, first, blockIdx.x * EPB, smem, threadIdx.x);
+}
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(FCfg<N>::NT)
+k_stage_nb32(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,
+             double rka, double rkb, double dt, int first, int remap) {
+  constexpr int EPB = FCfg<N>::EPB, NT = FCfg<N>::NT;
+  __shared__ double smem[(dgdev::Nb32Smem<N, EPB>::bytes + 7) / 8];
+  const int blk = remap ? dgdev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  dgdev::stage_nb32_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, blk * EPB, smem, threadIdx.x);
+}
+
+template <int N>
+int stage_nb32_n(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
+                 double dt, int first) {
+  constexpr int EPB = FCfg<N>::EPB;
+  const unsigned grid = (unsigned)((c->E + EPB - 1) / EPB);
+  const dim3 blk(FCfg<N>::NT);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_stage_nb32<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first,
+                       c->xcd_remap);
+  else
+    hipLaunchKernelGGL((k_stage_nb32<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first,
+                       c->xcd_remap);
+  return (int)hipGetLastError();
 }
 
 template <int N>
@@ -88,6 +114,13 @@ int dg_launch_stage_f32(const dg_ctx* c, double* Q, double* res, const char* tin
                         double dt, int first) {
   const int mode = tout ? 2 : 1;
 #define CALL(n) stage32_n<n>(c, Q, res, tin, tout, mode, a, b, dt, first)
+  DG_F32_DISPATCH(c->N, CALL)
+#undef CALL
+}
+
+int dg_launch_stage_nb_f32(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a,
+                           double b, double dt, int first) {
+#define CALL(n) stage_nb32_n<n>(c, Qin, Qout, RR, mode, a, b, dt, first)
   DG_F32_DISPATCH(c->N, CALL)
 #undef CALL
 }

@@ -143,7 +143,9 @@ def test_tgv_c2_steps_vs_oracle(dgm):
     dq = np.abs(Qh - Qo).reshape(5, -1).max(axis=1)
     ch = np.abs(Qo - Q0).reshape(5, -1).max(axis=1)
     print("change-relative", dq / ch)
-    assert np.all(dq <= 1e-10 * ch)
+    # after 3 steps the density changes by ~3e-6 of itself, so FP64 rounding
+    # of the state alone is ~1e-10 of the change
+    assert np.all(dq <= 1e-8 * ch)
 
 
 def test_integrals_and_wavespeed(dgm):
@@ -204,8 +206,9 @@ def test_tgv_c2_full_run_drift(dgm):
     assert s.check_state(Q)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("p", [1, 3, 4, 6])
-def test_exchange_schemes_bitwise_equal(dgm, p):
+def test_exchange_schemes_bitwise_equal(dgm, p, prec):
     """Neighbour reads (with and without the XCD block mapping) and the
     face-trace buffers give bit-identical RHS, single stages (odd stage
     count: ping-pong copy back) and multi-step runs."""
@@ -214,7 +217,7 @@ def test_exchange_schemes_bitwise_equal(dgm, p):
     Q0 = _dev(W.random_smooth(n, p, seed=90 + p, noise=0.02))
     outs = []
     for exch, remap in [(dgm.DG_EXCHANGE_TRACES, 1), (dgm.DG_EXCHANGE_NEIGHBOUR, 1), (dgm.DG_EXCHANGE_NEIGHBOUR, 0)]:
-        s = dgm.Solver(n, p)
+        s = dgm.Solver(n, p, precision=dgm.DG_FP64 if prec == "fp64" else dgm.DG_FP32_MFMA)
         s.set_option(dgm.DG_OPT_EXCHANGE, exch)
         s.set_option(dgm.DG_OPT_XCD_REMAP, remap)
         dt = 0.2 * s.dt_cfl(Q0, 1.0)
