@@ -61,9 +61,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision):
+def measured_traffic(workload, precision, options):
     """HBM bytes per launch of the stage kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source with the
+    same options."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -71,7 +72,7 @@ def measured_traffic(workload, precision):
     except (OSError, ValueError):
         return None
     ent = rec.get(f"{workload}:{precision}")
-    if not ent or ent.get("kernel_src") != kernel_source_hash():
+    if not ent or ent.get("kernel_src") != kernel_source_hash() or ent.get("options") != options:
         return None
     return ent.get("bytes_per_launch")
 
@@ -183,7 +184,14 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--exchange", default="neighbour", choices=["neighbour", "traces"],
                     help="how a stage obtains its neighbours' face traces (FP64 path)")
-    ap.add_argument("--xcd-remap", action="store_true", help="XCD-aware workgroup mapping (default off)")
+    ap.add_argument("--xcd-remap", type=int, default=None, choices=[0, 1],
+                    help="1: each XCD takes a contiguous part of the visiting order (default: library's)")
+    ap.add_argument("--order", default=None, choices=["linear", "pencil"],
+                    help="element-block visiting order of the stage kernel (default: library's)")
+    ap.add_argument("--pencil-x", type=int, default=None, help="pencil extent along x in elements (0: row)")
+    ap.add_argument("--pencil-z", type=int, default=None, help="pencil extent along z in element planes")
+    ap.add_argument("--stream-stores", type=int, default=None, choices=[0, 1],
+                    help="non-temporal hints on the streamed state (default: library's)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, time a plain device-to-device copy of MIB MiB "
                          "(calibrates HBM byte counters; reports the copy bandwidth)")
@@ -232,7 +240,13 @@ def main():
     s = dg.Solver((n, n, n), p, L=L, precision=prec)
     s.set_option(dg.DG_OPT_EXCHANGE, dg.DG_EXCHANGE_NEIGHBOUR if args.exchange == "neighbour"
                  else dg.DG_EXCHANGE_TRACES)
-    s.set_option(dg.DG_OPT_XCD_REMAP, 1 if args.xcd_remap else 0)
+    for key, val in ((dg.DG_OPT_XCD_REMAP, args.xcd_remap),
+                     (dg.DG_OPT_ORDER, None if args.order is None
+                      else dg.DG_ORDER_PENCIL if args.order == "pencil" else dg.DG_ORDER_LINEAR),
+                     (dg.DG_OPT_PENCIL_X, args.pencil_x), (dg.DG_OPT_PENCIL_Z, args.pencil_z),
+                     (dg.DG_OPT_STREAM_STORES, args.stream_stores)):
+        if val is not None:
+            s.set_option(key, val)
     dof = s.num_dof
     Q0 = torch.from_numpy(W.tgv(n, p)).cuda()
     dt = s.dt_cfl(Q0, 0.3)
@@ -265,8 +279,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "elements": n ** 3, "p": p,
                    "dof": dof, "precision": args.precision, "dt": dt,
-                   "exchange": args.exchange if args.precision == "fp64" else "traces",
-                   "xcd_remap": bool(args.xcd_remap)},
+                   "options": s.options()},
     }
 
     if not args.no_roofline:
@@ -281,12 +294,12 @@ def main():
         avg_s = st_ms / st_n * 1e-3
         alg_bytes = ALG_BYTES_PER_DOF_STAGE * dof
         achieved = alg_bytes / avg_s / 1e9
-        traffic = measured_traffic(args.workload, args.precision)
+        traffic = measured_traffic(args.workload, args.precision, s.options())
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": ("k_stage_nb" if (args.exchange == "neighbour" and args.precision == "fp64")
-                                      else "k_stage32" if args.precision == "fp32" else "k_stage")
-                           + " (fused RHS + LSERK45 stage)",
+                           "kernel": {("neighbour", "fp64"): "k_stage_nb", ("neighbour", "fp32"): "k_stage_nb32",
+                                      ("traces", "fp64"): "k_stage", ("traces", "fp32"): "k_stage32"}[
+                                          (args.exchange, args.precision)] + " (fused RHS + LSERK45 stage)",
                            "avg_launch_us": avg_s * 1e6, "launches": st_n,
                            "alg_bytes_per_launch": alg_bytes}
         fl = flops_per_dof_stage(p + 1) * dof

@@ -358,7 +358,14 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
   c->stream = nullptr;
   c->precision = DG_FP64;
   c->exchange = DG_EXCHANGE_NEIGHBOUR;
-  c->xcd_remap = 0;
+  // Measured on MI355X: row pencils 4 planes deep, chunked per XCD, help
+  // up to N = 5 (several elements per workgroup); from N = 6 on (one element
+  // per workgroup) the index order is as fast.
+  c->order = c->N <= 5 ? DG_ORDER_PENCIL : DG_ORDER_LINEAR;
+  c->xcd_remap = c->N <= 5 ? 1 : 0;
+  c->pencil_x = 0;
+  c->pencil_z = 4;
+  c->stream_stores = 0;
   build_tables(c);
   g_err[0] = 0;
   return c;
@@ -445,7 +452,39 @@ int dg_set_option(dg_ctx* c, int key, int value) {
     c->xcd_remap = value ? 1 : 0;
     return DG_OK;
   }
+  if (key == DG_OPT_ORDER) {
+    if (value != DG_ORDER_LINEAR && value != DG_ORDER_PENCIL) return fail(DG_EINVAL, "unknown order %d", value);
+    c->order = value;
+    return DG_OK;
+  }
+  if (key == DG_OPT_PENCIL_X) {
+    if (value < 0) return fail(DG_EINVAL, "pencil x extent %d < 0", value);
+    c->pencil_x = value;
+    return DG_OK;
+  }
+  if (key == DG_OPT_PENCIL_Z) {
+    if (value < 1) return fail(DG_EINVAL, "pencil z extent %d < 1", value);
+    c->pencil_z = value;
+    return DG_OK;
+  }
+  if (key == DG_OPT_STREAM_STORES) {
+    c->stream_stores = value ? 1 : 0;
+    return DG_OK;
+  }
   return fail(DG_EINVAL, "unknown option %d", key);
+}
+
+int dg_get_option(const dg_ctx* c, int key, int* value) {
+  if (!c || !value) return fail(DG_EINVAL, "NULL argument");
+  switch (key) {
+    case DG_OPT_EXCHANGE: *value = c->exchange; return DG_OK;
+    case DG_OPT_XCD_REMAP: *value = c->xcd_remap; return DG_OK;
+    case DG_OPT_ORDER: *value = c->order; return DG_OK;
+    case DG_OPT_PENCIL_X: *value = c->pencil_x; return DG_OK;
+    case DG_OPT_PENCIL_Z: *value = c->pencil_z; return DG_OK;
+    case DG_OPT_STREAM_STORES: *value = c->stream_stores; return DG_OK;
+    default: return fail(DG_EINVAL, "unknown option %d", key);
+  }
 }
 
 size_t dg_workspace_bytes(const dg_ctx* c) {

@@ -49,9 +49,11 @@ __device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, const dou
 #define DG_CASE(n, e)                                                                                  \
   case n * 64 + e:                                                                                     \
     if (F32)                                                                                           \
-      dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, smem, tid);    \
+      dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0,                \
+                                              min(e, I.tab.E - e0), false, smem, tid);                 \
     else                                                                                               \
-      dgdev::stage_nb_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, smem, tid);      \
+      dgdev::stage_nb_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0,                  \
+                                            min(e, I.tab.E - e0), false, smem, tid);                   \
     break;
   switch (key) { DG_BATCH_VARIANTS(DG_CASE) default: break; }
 #undef DG_CASE

@@ -37,25 +37,25 @@ k_stage32(DGTables tb, double* __restrict__ Q, double* __restrict__ RR, const ch
 template <int N, int MODE>
 __global__ void __launch_bounds__(FCfg<N>::NT)
 k_stage_nb32(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,
-             double rka, double rkb, double dt, int first, int remap) {
+             double rka, double rkb, double dt, int first, DGOrder ord) {
   constexpr int EPB = FCfg<N>::EPB, NT = FCfg<N>::NT;
   __shared__ double smem[(dgdev::Nb32Smem<N, EPB>::bytes + 7) / 8];
-  const int blk = remap ? dgdev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-  dgdev::stage_nb32_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, blk * EPB, smem, threadIdx.x);
+  int e0, ne;
+  dgdev::block_elements<EPB>(tb, ord, blockIdx.x, gridDim.x, e0, ne);
+  dgdev::stage_nb32_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, ord.stream != 0, smem,
+                                           threadIdx.x);
 }
 
 template <int N>
 int stage_nb32_n(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
                  double dt, int first) {
-  constexpr int EPB = FCfg<N>::EPB;
-  const unsigned grid = (unsigned)((c->E + EPB - 1) / EPB);
+  unsigned grid;
+  const DGOrder ord = dg_order(c, FCfg<N>::EPB, &grid);
   const dim3 blk(FCfg<N>::NT);
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage_nb32<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first,
-                       c->xcd_remap);
+    hipLaunchKernelGGL((k_stage_nb32<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
   else
-    hipLaunchKernelGGL((k_stage_nb32<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first,
-                       c->xcd_remap);
+    hipLaunchKernelGGL((k_stage_nb32<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
   return (int)hipGetLastError();
 }
 

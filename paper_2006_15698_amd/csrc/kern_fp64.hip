@@ -44,16 +44,18 @@ k_stage(DGTables tb, double* __restrict__ Q, double* __restrict__ RR,
   dgdev::stage_body<N, MODE, EPB, NT>(tb, Q, RR, Tin, Tout, rka, rkb, dt, first, blockIdx.x * EPB, smem, threadIdx.x);
 }
 
-// Neighbour-read variant: Qin -> Qout (different buffers), no trace buffers.
-// remap != 0: XCD-aware workgroup -> block mapping.
+// Neighbour-read variant: Qin -> Qout (different buffers), no trace buffers;
+// element blocks visited in the order `ord`.
 template <int N, int MODE>
 __global__ void __launch_bounds__(Cfg<N>::NT)
 k_stage_nb(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,
-           double rka, double rkb, double dt, int first, int remap) {
+           double rka, double rkb, double dt, int first, DGOrder ord) {
   constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
   __shared__ double smem[dgdev::Fp64Smem<N, EPB>::size];
-  const int blk = remap ? dgdev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-  dgdev::stage_nb_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, blk * EPB, smem, threadIdx.x);
+  int e0, ne;
+  dgdev::block_elements<EPB>(tb, ord, blockIdx.x, gridDim.x, e0, ne);
+  dgdev::stage_nb_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, ord.stream != 0, smem,
+                                         threadIdx.x);
 }
 
 // ---- reductions -----------------------------------------------------------
@@ -165,14 +167,13 @@ int launch_stage_n(const dg_ctx* c, double* Q, double* RR, const double* Tin, do
 template <int N>
 int launch_stage_nb_n(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
                       double dt, int first) {
-  constexpr int EPB = Cfg<N>::EPB;
-  const unsigned grid = (unsigned)((c->E + EPB - 1) / EPB);
+  unsigned grid;
+  const DGOrder ord = dg_order(c, Cfg<N>::EPB, &grid);
   const dim3 blk(Cfg<N>::NT);
-  const int remap = c->xcd_remap;
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage_nb<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, remap);
+    hipLaunchKernelGGL((k_stage_nb<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
   else
-    hipLaunchKernelGGL((k_stage_nb<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, remap);
+    hipLaunchKernelGGL((k_stage_nb<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
   return (int)hipGetLastError();
 }
 

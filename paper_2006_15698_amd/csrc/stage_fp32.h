@@ -24,6 +24,7 @@
 
 #include "dg_internal.h"
 #include "stage_fp64.h"
+#include "stage_nb.h"
 
 namespace dgdev {
 
@@ -404,11 +405,13 @@ struct Nb32Smem {
 // trace_dev), so both sides of a face see the same bits.  The volume
 // contraction runs one direction at a time: flux deviations of direction d
 // in sF, matrix-core products into sV, then the FP64 assembly.
-// MODE 0: RR = dQ/dt.  MODE 1: RK stage (res = RR in place).
+// Elements [e0, e0 + ne).  MODE 0: RR = dQ/dt.  MODE 1: RK stage (res = RR
+// in place).  nt: non-temporal res read and stores.
 template <int N, int MODE, int EPB, int NT>
 __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double* __restrict__ Qin,
                                                 double* __restrict__ Qout, double* __restrict__ RR, double rka,
-                                                double rkb, double dt, int first, int e0, double* smem, int tid) {
+                                                double rkb, double dt, int first, int e0, int ne, bool nt,
+                                                double* smem, int tid) {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int NODES = EPB * N3, FP = EPB * N2;
   constexpr int NITEM = 6 * FP;
@@ -456,7 +459,7 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
   const int t = tid - el * N3;
   const int ni = t % N, nj = (t / N) % N, nk = t / N2;
   const int e = e0 + el;
-  const bool act = nthr && e < E;
+  const bool act = nthr && el < ne;
   const int64_t gofs = (int64_t)e * N3 + t;
   double q[5], r[5];
   if (act) {
@@ -469,7 +472,7 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
   for (int f = 0; f < 5; ++f) r[f] = 0.0;
   if (MODE != 0 && act && !first) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + gofs];
+    for (int f = 0; f < 5; ++f) r[f] = ld_stream(RR + f * EN3 + gofs, nt);
   }
   if (nthr) {
 #pragma unroll
@@ -484,7 +487,7 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
     const int fel = rem / N2;
     const int pt = rem - fel * N2;
     const int ee = e0 + fel;
-    if (it < NITEM && ee < E) {
+    if (it < NITEM && fel < ne) {
       const int d = face >> 1, side = face & 1;
       const int nbe = neighbour(tb.nx, tb.ny, tb.nz, ee, d, side ? 1 : -1);
       const double* base = Qin + (int64_t)nbe * N3;
@@ -612,7 +615,7 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
   if (MODE == 0) {
     if (act) {
 #pragma unroll
-      for (int f = 0; f < 5; ++f) RR[f * EN3 + gofs] = acc5[f];
+      for (int f = 0; f < 5; ++f) st_stream(RR + f * EN3 + gofs, acc5[f], nt);
     }
   } else {
 #pragma unroll
@@ -623,8 +626,8 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
     if (act) {
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
-        Qout[f * EN3 + gofs] = q[f];
-        RR[f * EN3 + gofs] = r[f];
+        st_stream(Qout + f * EN3 + gofs, q[f], nt);
+        st_stream(RR + f * EN3 + gofs, r[f], nt);
       }
     }
   }

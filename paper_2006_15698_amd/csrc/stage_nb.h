@@ -19,18 +19,61 @@ namespace dgdev {
 // of blocks: workgroups are dispatched round robin over the 8 XCDs, so
 // workgroup w runs on XCD w % 8; its block is the (w / 8)-th of that XCD's
 // slab.  A bijection on [0, nblk) for any nblk.
-__device__ __forceinline__ int xcd_block(int w, int nblk) {
+__host__ __device__ __forceinline__ int xcd_block(int w, int nblk) {
   const int q = nblk >> 3, r = nblk & 7;
   const int x = w & 7, i = w >> 3;
   return x * q + (x < r ? x : r) + i;
 }
 
-// MODE 0: RR = dQ/dt (Qout unused).  MODE 1: RK stage, res in place,
-// Qout = Qin + b res.  smem: Fp64Smem<N,EPB>::size doubles.
+__host__ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+// Elements [e0, e0 + ne) of workgroup w of nblk under the visiting order o
+// (see DGOrder).  Every value is uniform over the workgroup.
+
+template <int EPB>
+__host__ __device__ __forceinline__ void block_elements(const DGTables& tb, const DGOrder& o, int w, int nblk,
+                                                        int& e0, int& ne) {
+  const int s = o.xcd ? xcd_block(w, nblk) : w;
+  if (!o.pencil) {
+    e0 = s * EPB;
+    ne = imin(EPB, tb.E - e0);
+    return;
+  }
+  const int slab = o.nxb * tb.ny * o.tz;     // blocks of a full z-slab
+  const int pz = s / slab;
+  int r = s - pz * slab;
+  const int tz = imin(o.tz, tb.nz - pz * o.tz);
+  const int pen = tb.ny * tz * o.tx;         // blocks of a full pencil of this slab
+  const int px = r / pen;
+  r -= px * pen;
+  const int tx = imin(o.tx, o.nxb - px * o.tx);
+  const int y = r / (tz * tx);
+  r -= y * (tz * tx);
+  const int zz = r / tx;
+  const int x0 = (px * o.tx + r - zz * tx) * EPB;
+  e0 = ((pz * o.tz + zz) * tb.ny + y) * tb.nx + x0;
+  ne = imin(EPB, tb.nx - x0);
+}
+
+// Streamed loads and stores; non-temporal when `nt` (uniform).
+__device__ __forceinline__ double ld_stream(const double* p, bool nt) {
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+__device__ __forceinline__ void st_stream(double* p, double v, bool nt) {
+  if (nt)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// Elements [e0, e0 + ne) with ne <= EPB.  MODE 0: RR = dQ/dt (Qout
+// unused).  MODE 1: RK stage, res in place, Qout = Qin + b res.  smem:
+// Fp64Smem<N,EPB>::size doubles.  nt: non-temporal res read and stores.
 template <int N, int MODE, int EPB, int NT>
 __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* __restrict__ Qin,
                                               double* __restrict__ Qout, double* __restrict__ RR, double rka,
-                                              double rkb, double dt, int first, int e0, double* smem, int tid) {
+                                              double rkb, double dt, int first, int e0, int ne, bool nt,
+                                              double* smem, int tid) {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int NODES = EPB * N3, FP = EPB * N2;
   constexpr int NITEM = 6 * FP;
@@ -69,7 +112,7 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   const int t = tid - el * N3;
   const int ni = t % N, nj = (t / N) % N, nk = t / N2;
   const int e = e0 + el;
-  const bool act = nthr && e < E;
+  const bool act = nthr && el < ne;
   const int64_t gofs = (int64_t)e * N3 + t;
   double q[5], r[5];
   if (act) {
@@ -82,7 +125,7 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   for (int f = 0; f < 5; ++f) r[f] = 0.0;
   if (MODE != 0 && act && !first) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + gofs];
+    for (int f = 0; f < 5; ++f) r[f] = ld_stream(RR + f * EN3 + gofs, nt);
   }
   if (nthr) {
 #pragma unroll
@@ -97,7 +140,7 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     const int fel = rem / N2;
     const int pt = rem - fel * N2;
     const int ee = e0 + fel;
-    if (it < NITEM && ee < E) {
+    if (it < NITEM && fel < ne) {
       const int d = face >> 1, side = face & 1;
       const int nbe = neighbour(tb.nx, tb.ny, tb.nz, ee, d, side ? 1 : -1);
       // the neighbour's face on the other side: its -d face for our +d face
@@ -181,7 +224,7 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   if (MODE == 0) {
     if (act) {
 #pragma unroll
-      for (int f = 0; f < 5; ++f) RR[f * EN3 + gofs] = acc[f];
+      for (int f = 0; f < 5; ++f) st_stream(RR + f * EN3 + gofs, acc[f], nt);
     }
   } else {
 #pragma unroll
@@ -192,8 +235,8 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     if (act) {
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
-        Qout[f * EN3 + gofs] = q[f];
-        RR[f * EN3 + gofs] = r[f];
+        st_stream(Qout + f * EN3 + gofs, q[f], nt);
+        st_stream(RR + f * EN3 + gofs, r[f], nt);
       }
     }
   }

@@ -38,8 +38,17 @@ DG_FP64 = 0
 DG_FP32_MFMA = 1
 DG_OPT_EXCHANGE = 1
 DG_OPT_XCD_REMAP = 2
+DG_OPT_ORDER = 3
+DG_OPT_PENCIL_X = 4
+DG_OPT_PENCIL_Z = 5
+DG_OPT_STREAM_STORES = 6
 DG_EXCHANGE_TRACES = 0
 DG_EXCHANGE_NEIGHBOUR = 1
+DG_ORDER_LINEAR = 0
+DG_ORDER_PENCIL = 1
+OPTION_NAMES = {DG_OPT_EXCHANGE: "exchange", DG_OPT_XCD_REMAP: "xcd_remap", DG_OPT_ORDER: "order",
+                DG_OPT_PENCIL_X: "pencil_x", DG_OPT_PENCIL_Z: "pencil_z",
+                DG_OPT_STREAM_STORES: "stream_stores"}
 
 ERROR_NAMES = {DG_EINVAL: "DG_EINVAL", DG_EUNSUPPORTED: "DG_EUNSUPPORTED", DG_EHIP: "DG_EHIP",
                DG_EALIAS: "DG_EALIAS", DG_ENONPHYSICAL: "DG_ENONPHYSICAL",
@@ -82,6 +91,7 @@ _SIGS = {
     "dg_batch_rk_steps": (_i, [_vp, _vp, _vp, _i]),
     "dg_batch_graph_steps": (_i, [_vp, _vp, _vp, _i]),
     "dg_set_option": (_i, [_vp, _i, _i]),
+    "dg_get_option": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_int)]),
     "dg_set_timing": (_i, [_vp, _i]),
     "dg_timing_read": (_i, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -164,6 +174,12 @@ def dg_set_precision(ctx, mode):
 
 def dg_set_option(ctx, key, value):
     return _check(_lib.dg_set_option(ctx, int(key), int(value)))
+
+
+def dg_get_option(ctx, key):
+    v = ctypes.c_int(0)
+    _check(_lib.dg_get_option(ctx, int(key), ctypes.byref(v)))
+    return v.value
 
 
 def dg_workspace_bytes(ctx):
@@ -438,6 +454,13 @@ class Solver:
 
     def set_option(self, key, value):
         dg_set_option(self.ctx, key, value)
+
+    def get_option(self, key):
+        return dg_get_option(self.ctx, key)
+
+    def options(self):
+        """All tuning options by name."""
+        return {name: dg_get_option(self.ctx, k) for k, name in OPTION_NAMES.items()}
 
     def _s(self):
         dg_set_stream(self.ctx, None)
