@@ -190,8 +190,6 @@ def main():
                     help="element-block visiting order of the stage kernel (default: library's)")
     ap.add_argument("--pencil-x", type=int, default=None, help="pencil extent along x in elements (0: row)")
     ap.add_argument("--pencil-z", type=int, default=None, help="pencil extent along z in element planes")
-    ap.add_argument("--stream-stores", type=int, default=None, choices=[0, 1],
-                    help="non-temporal hints on the streamed state (default: library's)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, time a plain device-to-device copy of MIB MiB "
                          "(calibrates HBM byte counters; reports the copy bandwidth)")
@@ -243,8 +241,7 @@ def main():
     for key, val in ((dg.DG_OPT_XCD_REMAP, args.xcd_remap),
                      (dg.DG_OPT_ORDER, None if args.order is None
                       else dg.DG_ORDER_PENCIL if args.order == "pencil" else dg.DG_ORDER_LINEAR),
-                     (dg.DG_OPT_PENCIL_X, args.pencil_x), (dg.DG_OPT_PENCIL_Z, args.pencil_z),
-                     (dg.DG_OPT_STREAM_STORES, args.stream_stores)):
+                     (dg.DG_OPT_PENCIL_X, args.pencil_x), (dg.DG_OPT_PENCIL_Z, args.pencil_z)):
         if val is not None:
             s.set_option(key, val)
     dof = s.num_dof

@@ -101,22 +101,20 @@ int dg_set_precision(dg_ctx* ctx, int mode);
  *   state to a workspace buffer that the next launch reads.
  *   Both give bitwise identical results.
  * The remaining options change only the order in which the neighbour-read
- * stage visits elements and the cache hints of its loads and stores; the
- * results are bitwise the same for every setting.
- * DG_OPT_ORDER: DG_ORDER_LINEAR visits blocks of consecutive elements in
- *   index order; DG_ORDER_PENCIL visits pencils of PENCIL_X x PENCIL_Z
- *   elements (x by z) swept along y, so that every neighbour of an element
- *   is visited shortly before or after it and is still in L2.  Needs no
- *   condition on the mesh (ragged pencils and rows are handled).
+ * stage visits elements; the results are bitwise the same for every
+ * setting.
+ * DG_OPT_ORDER: the stage kernel works on blocks of consecutive elements of
+ *   one x-row.  DG_ORDER_LINEAR visits them in index order;
+ *   DG_ORDER_PENCIL visits pencils of PENCIL_X x PENCIL_Z elements (x by z)
+ *   swept along y, so that every neighbour of an element is visited shortly
+ *   before or after it and is still in L2.  Needs no condition on the mesh
+ *   (ragged pencils and rows are handled).
  * DG_OPT_PENCIL_X: elements of a pencil along x (rounded up to the
  *   kernel's block of elements; 0 = the whole row).
  * DG_OPT_PENCIL_Z: element planes of a pencil along z (>= 1).
  * DG_OPT_XCD_REMAP: 1 gives each of the 8 XCDs of the MI355X (each with
  *   its own L2) a contiguous part of the visiting order; 0 leaves the
  *   hardware's round-robin spread of workgroups over the XCDs.
- * DG_OPT_STREAM_STORES: 1 marks the residual read and the state and
- *   residual writes non-temporal, leaving L2 to the state that neighbours
- *   read again.
  * Defaults: the fastest measured setting for the mesh and p (see
  * dg_get_option). */
 enum {
@@ -124,8 +122,7 @@ enum {
   DG_OPT_XCD_REMAP = 2,
   DG_OPT_ORDER = 3,
   DG_OPT_PENCIL_X = 4,
-  DG_OPT_PENCIL_Z = 5,
-  DG_OPT_STREAM_STORES = 6
+  DG_OPT_PENCIL_Z = 5
 };
 enum { DG_EXCHANGE_TRACES = 0, DG_EXCHANGE_NEIGHBOUR = 1 };
 enum { DG_ORDER_LINEAR = 0, DG_ORDER_PENCIL = 1 };

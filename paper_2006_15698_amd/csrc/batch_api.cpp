@@ -59,7 +59,10 @@ void build_items(dg_batch* b) {
   for (int i = 0; i < b->count; ++i) {
     DGBatchInst& I = b->inst[i];
     I.epb = b->epb_for_N[I.N];
-    for (int e0 = 0; e0 < I.tab.E; e0 += I.epb) b->items.push_back(make_int2(i, e0));
+    // blocks of up to epb consecutive elements of one x-row
+    const int nx = I.tab.nx, rows = I.tab.ny * I.tab.nz;
+    for (int row = 0; row < rows; ++row)
+      for (int x0 = 0; x0 < nx; x0 += I.epb) b->items.push_back(make_int2(i, row * nx + x0));
   }
   b->uploaded = false;
 }

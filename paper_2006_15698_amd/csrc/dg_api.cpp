@@ -358,14 +358,12 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
   c->stream = nullptr;
   c->precision = DG_FP64;
   c->exchange = DG_EXCHANGE_NEIGHBOUR;
-  // Measured on MI355X: row pencils 4 planes deep, chunked per XCD, help
-  // up to N = 5 (several elements per workgroup); from N = 6 on (one element
-  // per workgroup) the index order is as fast.
-  c->order = c->N <= 5 ? DG_ORDER_PENCIL : DG_ORDER_LINEAR;
-  c->xcd_remap = c->N <= 5 ? 1 : 0;
-  c->pencil_x = 0;
-  c->pencil_z = 4;
-  c->stream_stores = 0;
+  // Fastest measured on MI355X (32^3 p=3, 48^3 p=4, 40^3 p=6): pencils of
+  // 16 x 8 elements, each XCD taking a contiguous part of the order.
+  c->order = DG_ORDER_PENCIL;
+  c->xcd_remap = 1;
+  c->pencil_x = 16;
+  c->pencil_z = 8;
   build_tables(c);
   g_err[0] = 0;
   return c;
@@ -467,10 +465,6 @@ int dg_set_option(dg_ctx* c, int key, int value) {
     c->pencil_z = value;
     return DG_OK;
   }
-  if (key == DG_OPT_STREAM_STORES) {
-    c->stream_stores = value ? 1 : 0;
-    return DG_OK;
-  }
   return fail(DG_EINVAL, "unknown option %d", key);
 }
 
@@ -482,7 +476,6 @@ int dg_get_option(const dg_ctx* c, int key, int* value) {
     case DG_OPT_ORDER: *value = c->order; return DG_OK;
     case DG_OPT_PENCIL_X: *value = c->pencil_x; return DG_OK;
     case DG_OPT_PENCIL_Z: *value = c->pencil_z; return DG_OK;
-    case DG_OPT_STREAM_STORES: *value = c->stream_stores; return DG_OK;
     default: return fail(DG_EINVAL, "unknown option %d", key);
   }
 }

@@ -52,19 +52,16 @@ struct dg_ctx {
   int order;      // DG_ORDER_LINEAR or DG_ORDER_PENCIL
   int pencil_x;   // pencil extent along x in elements (0: whole row)
   int pencil_z;   // pencil extent along z in element planes
-  int stream_stores;
 };
 
 // Order in which a neighbour-read stage launch visits its element blocks
-// (kernel argument).  Linear: block b = elements [b EPB, b EPB + EPB).
-// Pencil: a block is EPB consecutive elements of one x-row (the last block
-// of a row may be short); blocks are visited z-slab by z-slab, inside a
-// slab pencil by pencil along x, inside a pencil y-row by y-row, and inside
-// that z-plane by z-plane, x fastest.
+// (kernel argument).  A block is EPB consecutive elements of one x-row (the
+// last block of a row may be short).  Blocks are visited z-slab by z-slab
+// (tz planes), inside a slab pencil by pencil along x (tx blocks), inside a
+// pencil y-row by y-row, and inside that z-plane by z-plane, x fastest.
+// Index order is the special case of whole-row pencils one plane deep.
 struct DGOrder {
-  int pencil;   // 0 linear, 1 pencil
   int xcd;      // chunk the visiting order per XCD
-  int stream;   // non-temporal hints on the streamed state
   int nxb;      // blocks per x-row
   int tx;       // blocks of a pencil along x
   int tz;       // element planes of a pencil along z
@@ -74,14 +71,13 @@ struct DGOrder {
 // elements per block.
 inline DGOrder dg_order(const dg_ctx* c, int epb, unsigned* grid) {
   DGOrder o;
-  o.pencil = c->order == DG_ORDER_PENCIL;
+  const bool pencil = c->order == DG_ORDER_PENCIL;
   o.xcd = c->xcd_remap;
-  o.stream = c->stream_stores;
   o.nxb = (c->nx + epb - 1) / epb;
-  const int px = c->pencil_x > 0 && c->pencil_x < c->nx ? c->pencil_x : c->nx;
+  const int px = pencil && c->pencil_x > 0 && c->pencil_x < c->nx ? c->pencil_x : c->nx;
   o.tx = (px + epb - 1) / epb;
-  o.tz = c->pencil_z < 1 ? 1 : (c->pencil_z > c->nz ? c->nz : c->pencil_z);
-  *grid = o.pencil ? (unsigned)((int64_t)o.nxb * c->ny * c->nz) : (unsigned)((c->E + epb - 1) / epb);
+  o.tz = !pencil || c->pencil_z < 1 ? 1 : (c->pencil_z > c->nz ? c->nz : c->pencil_z);
+  *grid = (unsigned)((int64_t)o.nxb * c->ny * c->nz);
   return o;
 }
 

@@ -1,8 +1,8 @@
 // Batched persistent kernels: many independent periodic meshes of uneven
 // size and polynomial degree advanced by one launch per RK stage.
 //
-// A work list of (mesh, first element) items, one item per workgroup's worth
-// of elements, is walked by a persistent grid (static round robin: item k
+// A work list of (mesh, first element) items, one item per block of up to EPB
+// consecutive elements of one x-row, is walked by a persistent grid (static round robin: item k
 // belongs to block k mod gridDim).  Each item runs the same fused
 // neighbour-read stage body as the single-mesh kernel (stage_nb.h /
 // stage_fp32.h) with the compile-time degree N and elements-per-workgroup
@@ -24,7 +24,7 @@ constexpr int BNT = 256;
   X(2, 8) X(2, 16) X(3, 4) X(3, 9) X(4, 2) X(4, 4) X(5, 1) X(5, 2) X(6, 1)
 
 template <int N, int EPB>
-constexpr int smax64() { return dgdev::Fp64Smem<N, EPB>::size; }
+constexpr int smax64() { return dgdev::NbSmem<N, EPB>::size; }
 template <int N, int EPB>
 constexpr int smax32() { return dgdev::Nb32Smem<N, EPB>::bytes; }
 
@@ -46,14 +46,15 @@ __device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, const dou
   const double* qi = Qin + I.qoff;
   double* qo = Qout ? Qout + I.qoff : nullptr;
   double* rr = RR + I.qoff;
+  // items are row-aligned blocks: the last block of a row may be short
+  const int x0 = e0 % I.tab.nx;
+  const int ne = dgdev::imin(I.epb, I.tab.nx - x0);
 #define DG_CASE(n, e)                                                                                  \
   case n * 64 + e:                                                                                     \
     if (F32)                                                                                           \
-      dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0,                \
-                                              min(e, I.tab.E - e0), false, smem, tid);                 \
+      dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid); \
     else                                                                                               \
-      dgdev::stage_nb_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0,                  \
-                                            min(e, I.tab.E - e0), false, smem, tid);                   \
+      dgdev::stage_nb_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid);   \
     break;
   switch (key) { DG_BATCH_VARIANTS(DG_CASE) default: break; }
 #undef DG_CASE

@@ -42,8 +42,7 @@ k_stage_nb32(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Q
   __shared__ double smem[(dgdev::Nb32Smem<N, EPB>::bytes + 7) / 8];
   int e0, ne;
   dgdev::block_elements<EPB>(tb, ord, blockIdx.x, gridDim.x, e0, ne);
-  dgdev::stage_nb32_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, ord.stream != 0, smem,
-                                           threadIdx.x);
+  dgdev::stage_nb32_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, smem, threadIdx.x);
 }
 
 template <int N>

@@ -51,11 +51,10 @@ __global__ void __launch_bounds__(Cfg<N>::NT)
 k_stage_nb(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,
            double rka, double rkb, double dt, int first, DGOrder ord) {
   constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
-  __shared__ double smem[dgdev::Fp64Smem<N, EPB>::size];
+  __shared__ double smem[dgdev::NbSmem<N, EPB>::size];
   int e0, ne;
   dgdev::block_elements<EPB>(tb, ord, blockIdx.x, gridDim.x, e0, ne);
-  dgdev::stage_nb_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, ord.stream != 0, smem,
-                                         threadIdx.x);
+  dgdev::stage_nb_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, smem, threadIdx.x);
 }
 
 // ---- reductions -----------------------------------------------------------

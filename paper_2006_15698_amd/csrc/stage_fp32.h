@@ -406,12 +406,12 @@ struct Nb32Smem {
 // contraction runs one direction at a time: flux deviations of direction d
 // in sF, matrix-core products into sV, then the FP64 assembly.
 // Elements [e0, e0 + ne).  MODE 0: RR = dQ/dt.  MODE 1: RK stage (res = RR
-// in place).  nt: non-temporal res read and stores.
+// in place).
 template <int N, int MODE, int EPB, int NT>
 __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double* __restrict__ Qin,
                                                 double* __restrict__ Qout, double* __restrict__ RR, double rka,
-                                                double rkb, double dt, int first, int e0, int ne, bool nt,
-                                                double* smem, int tid) {
+                                                double rkb, double dt, int first, int e0, int ne, double* smem,
+                                                int tid) {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int NODES = EPB * N3, FP = EPB * N2;
   constexpr int NITEM = 6 * FP;
@@ -472,7 +472,7 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
   for (int f = 0; f < 5; ++f) r[f] = 0.0;
   if (MODE != 0 && act && !first) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = ld_stream(RR + f * EN3 + gofs, nt);
+    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + gofs];
   }
   if (nthr) {
 #pragma unroll
@@ -615,7 +615,7 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
   if (MODE == 0) {
     if (act) {
 #pragma unroll
-      for (int f = 0; f < 5; ++f) st_stream(RR + f * EN3 + gofs, acc5[f], nt);
+      for (int f = 0; f < 5; ++f) RR[f * EN3 + gofs] = acc5[f];
     }
   } else {
 #pragma unroll
@@ -626,8 +626,8 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
     if (act) {
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
-        st_stream(Qout + f * EN3 + gofs, q[f], nt);
-        st_stream(RR + f * EN3 + gofs, r[f], nt);
+        Qout[f * EN3 + gofs] = q[f];
+        RR[f * EN3 + gofs] = r[f];
       }
     }
   }

@@ -1,44 +1,48 @@
 // Device code of the FP64 DG Euler stage with neighbour reads.
 //
 // Same arithmetic as stage_body (stage_fp64.h), but the trace of a
-// neighbour on the shared face is interpolated directly from the
-// neighbour's state (sum over its normal line of l_m(-+1) Q_m, the same
-// FMA chain as line_trace) instead of being read from a trace buffer that
-// the previous launch wrote.  The state is read from Qin and the updated
-// state written to Qout (a different buffer), so no launch reads what it
-// writes.  Per node and stage HBM traffic is Q in, res in, Q out, res out
+// neighbour on a shared face is interpolated from the neighbour's state in
+// the same launch (sum over its normal line of l_m(-+1) Q_m, the same FMA
+// chain as line_trace) instead of being read from a trace buffer that the
+// previous launch wrote.  The state is read from Qin and the updated state
+// written to Qout (a different buffer), so no launch reads what it writes.
+// Per node and stage the HBM traffic is Q in, res in, Q out, res out
 // (160 B) plus whatever neighbour reads miss the caches; there are no trace
 // buffers.  Results are bitwise those of stage_body.
+//
+// A workgroup owns a block of EPB consecutive elements of one x-row.
+//   x-faces: the two elements left and right of the block are loaded into
+//     LDS next to the block's own elements (coalesced), so every x-face
+//     trace, inner or outer, is interpolated from LDS.
+//   y- and z-faces: the neighbours of the block are the same EPB elements of
+//     an adjacent row, so each face's neighbour chunk has one base address
+//     for the whole workgroup; every wave handles points of a single face,
+//     so the face's direction and side are compile-time inside the loads.
 #pragma once
 
 #include "stage_fp64.h"
 
 namespace dgdev {
 
-// Workgroup -> element block mapping that gives each XCD a contiguous range
-// of blocks: workgroups are dispatched round robin over the 8 XCDs, so
-// workgroup w runs on XCD w % 8; its block is the (w / 8)-th of that XCD's
-// slab.  A bijection on [0, nblk) for any nblk.
+__host__ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+// Workgroup -> position in the visiting order that gives each XCD a
+// contiguous range: workgroups are dispatched round robin over the 8 XCDs,
+// so workgroup w runs on XCD w % 8 and is the (w / 8)-th of that XCD.  A
+// bijection on [0, nblk) for any nblk.
 __host__ __device__ __forceinline__ int xcd_block(int w, int nblk) {
   const int q = nblk >> 3, r = nblk & 7;
   const int x = w & 7, i = w >> 3;
   return x * q + (x < r ? x : r) + i;
 }
 
-__host__ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
-
 // Elements [e0, e0 + ne) of workgroup w of nblk under the visiting order o
-// (see DGOrder).  Every value is uniform over the workgroup.
-
+// (see DGOrder): always ne <= EPB consecutive elements of one x-row.  Every
+// value is uniform over the workgroup.
 template <int EPB>
 __host__ __device__ __forceinline__ void block_elements(const DGTables& tb, const DGOrder& o, int w, int nblk,
                                                         int& e0, int& ne) {
   const int s = o.xcd ? xcd_block(w, nblk) : w;
-  if (!o.pencil) {
-    e0 = s * EPB;
-    ne = imin(EPB, tb.E - e0);
-    return;
-  }
   const int slab = o.nxb * tb.ny * o.tz;     // blocks of a full z-slab
   const int pz = s / slab;
   int r = s - pz * slab;
@@ -55,42 +59,103 @@ __host__ __device__ __forceinline__ void block_elements(const DGTables& tb, cons
   ne = imin(EPB, tb.nx - x0);
 }
 
-// Streamed loads and stores; non-temporal when `nt` (uniform).
-__device__ __forceinline__ double ld_stream(const double* p, bool nt) {
-  return nt ? __builtin_nontemporal_load(p) : *p;
-}
-__device__ __forceinline__ void st_stream(double* p, double v, bool nt) {
-  if (nt)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
+// Shared-memory footprint (doubles) of stage_nb_body: the state of the
+// block and of its two x-neighbours (the flux of one direction reuses it),
+// the face fluxes and the 1-D tables.
+template <int N, int EPB>
+struct NbSmem {
+  static constexpr int N3 = N * N * N;
+  static constexpr int NH = (EPB + 2) * N3;
+  static constexpr int FP = EPB * N * N;
+  static constexpr int size = 5 * NH + 30 * FP + N * N + 4 * N;
+};
+
+// Face-point slots of a block: a slot is up to 64 points (one wave) of one
+// face's EPB N^2 points.  The y- and z-faces (2..5), whose neighbours come
+// from global memory, take the first slots; the x-faces (0, 1) the last.
+template <int N, int EPB>
+struct FaceSlots {
+  static constexpr int FP = EPB * N * N;
+  static constexpr int WPF = (FP + 63) / 64;   // slots per face
+  static constexpr int NS = 6 * WPF;
+  static constexpr int NYZ = 4 * WPF;
+  __host__ __device__ static constexpr int face(int s) { return s < NYZ ? 2 + s / WPF : (s - NYZ) / WPF; }
+  __host__ __device__ static constexpr int chunk(int s) { return s < NYZ ? s % WPF : (s - NYZ) % WPF; }
+};
+
+// Trace on our face (D, SIDE) of the neighbour chunk whose first node of
+// field 0 is at `base`: element fel of the chunk, tangential point pt.
+template <int N, int D, int SIDE>
+__device__ __forceinline__ void chunk_trace(const double* __restrict__ base, int64_t EN3, int fel, int pt,
+                                            const double* lmr, const double* lpr, double* out) {
+  constexpr int N3 = N * N * N;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double* qn = base + f * EN3 + fel * N3;
+    double v = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v = fma(SIDE ? lmr[m] : lpr[m], qn[tnode<N>(D, m, pt)], v);
+    out[f] = v;
+  }
 }
 
-// Elements [e0, e0 + ne) with ne <= EPB.  MODE 0: RR = dQ/dt (Qout
+// Lax-Friedrichs flux at point pt of face (D, SIDE) of the element whose
+// state is at `own` (LDS, field stride NH); the neighbour's trace comes
+// from LDS (`nbq`, x-faces) or from registers (`nbv`, y- and z-faces).
+template <int N, int D, int SIDE, bool LDSNB>
+__device__ __forceinline__ void face_flux(const double* own, const double* nbq, const double* nbv, int NH, int pt,
+                                          const double* sLm, const double* sLp, double gamma, double gm1,
+                                          double* fs) {
+  double qm[5], qp[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double o = line_trace<N>(own + f * NH, SIDE ? sLp : sLm, D, pt);
+    const double n = LDSNB ? line_trace<N>(nbq + f * NH, SIDE ? sLm : sLp, D, pt) : nbv[f];
+    qm[f] = SIDE ? o : n;
+    qp[f] = SIDE ? n : o;
+  }
+  lf_flux_d<D>(qm, qp, gamma, gm1, fs);
+}
+
+// Elements [e0, e0 + ne) of one x-row, ne <= EPB.  MODE 0: RR = dQ/dt (Qout
 // unused).  MODE 1: RK stage, res in place, Qout = Qin + b res.  smem:
-// Fp64Smem<N,EPB>::size doubles.  nt: non-temporal res read and stores.
+// NbSmem<N,EPB>::size doubles.
 template <int N, int MODE, int EPB, int NT>
 __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* __restrict__ Qin,
                                               double* __restrict__ Qout, double* __restrict__ RR, double rka,
-                                              double rkb, double dt, int first, int e0, int ne, bool nt,
-                                              double* smem, int tid) {
+                                              double rkb, double dt, int first, int e0, int ne, double* smem,
+                                              int tid) {
   constexpr int N2 = N * N, N3 = N2 * N;
-  constexpr int NODES = EPB * N3, FP = EPB * N2;
-  constexpr int NITEM = 6 * FP;
-  constexpr int IPT = (NITEM + NT - 1) / NT;
+  constexpr int NODES = EPB * N3, FP = EPB * N2, NH = (EPB + 2) * N3;
+  constexpr int NW = NT / 64;
+  using S = FaceSlots<N, EPB>;
+  constexpr int RND = (S::NS + NW - 1) / NW;     // slot rounds per wave
+  constexpr int RNDG = (S::NYZ + NW - 1) / NW;   // rounds that hold y/z slots
   static_assert(NODES <= NT, "one thread per node");
+  static_assert(NT % 64 == 0, "whole waves");
 
-  double* sQ = smem;                 // [5][NODES]
-  double* sF = sQ + 5 * NODES;       // [5][NODES]
-  double* sH = sF + 5 * NODES;       // [6][5][FP]
-  double* sDh = sH + 30 * FP;        // [N][N]
+  double* sQ = smem;             // [5][NH]: element slot 0 left neighbour, 1..ne own, ne+1 right neighbour
+  double* sF = smem;             // [5][NODES]: flux of one direction, reuses sQ after the face phase
+  double* sH = sQ + 5 * NH;      // [6][5][FP] face fluxes
+  double* sDh = sH + 30 * FP;    // [N][N]
   double* sLm = sDh + N * N;
   double* sLp = sLm + N;
   double* sLiftm = sLp + N;
   double* sLiftp = sLiftm + N;
 
-  const int E = tb.E;
-  const int64_t EN3 = (int64_t)E * N3;
+  const int nx = tb.nx, ny = tb.ny, nz = tb.nz;
+  const int64_t EN3 = (int64_t)tb.E * N3;
+  // block geometry, uniform: elements x0 .. x0 + ne - 1 of row (ey, ez)
+  const int row = e0 / nx;
+  const int x0 = e0 - row * nx;
+  const int ey = row % ny, ez = row / ny;
+  const int plane = nx * ny;
+  const int eym = ey == 0 ? e0 + (ny - 1) * nx : e0 - nx;
+  const int eyp = ey == ny - 1 ? e0 - (ny - 1) * nx : e0 + nx;
+  const int ezm = ez == 0 ? e0 + (nz - 1) * plane : e0 - plane;
+  const int ezp = ez == nz - 1 ? e0 - (nz - 1) * plane : e0 + plane;
+  const int exl = x0 == 0 ? e0 + nx - 1 : e0 - 1;      // left neighbour of the block
+  const int exr = x0 + ne == nx ? e0 - x0 : e0 + ne;    // right neighbour of the block
 
   for (int x = tid; x < N * N; x += NT) sDh[x] = tb.Dh[x];
   if (tid < N) {
@@ -106,14 +171,14 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     lpr[m] = tb.lp[m];
   }
 
-  // ---- A: this thread's node, residual register, neighbour traces
+  // ---- A: own node and residual; block and x-neighbours into LDS;
+  //         y/z neighbour traces into registers
   const bool nthr = tid < NODES;
   const int el = tid / N3;
   const int t = tid - el * N3;
   const int ni = t % N, nj = (t / N) % N, nk = t / N2;
-  const int e = e0 + el;
   const bool act = nthr && el < ne;
-  const int64_t gofs = (int64_t)e * N3 + t;
+  const int64_t gofs = (int64_t)e0 * N3 + tid;
   double q[5], r[5];
   if (act) {
 #pragma unroll
@@ -125,33 +190,33 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   for (int f = 0; f < 5; ++f) r[f] = 0.0;
   if (MODE != 0 && act && !first) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = ld_stream(RR + f * EN3 + gofs, nt);
+    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + gofs];
   }
-  if (nthr) {
+  if (act) {   // slots past ne + 1 stay unwritten: only points of absent elements read them
 #pragma unroll
-    for (int f = 0; f < 5; ++f) sQ[f * NODES + tid] = q[f];
+    for (int f = 0; f < 5; ++f) sQ[f * NH + N3 + tid] = q[f];
   }
-  double nb[IPT][5];
+  for (int x = tid; x < 2 * N3; x += NT) {
+    const int right = x >= N3;
+    const int tt = x - right * N3;
+    const double* hb = Qin + (int64_t)(right ? exr : exl) * N3 + tt;
+    double* hs = sQ + (right ? ne + 1 : 0) * N3 + tt;
 #pragma unroll
-  for (int u = 0; u < IPT; ++u) {
-    const int it = tid + u * NT;
-    const int face = it / FP;
-    const int rem = it - face * FP;
-    const int fel = rem / N2;
-    const int pt = rem - fel * N2;
-    const int ee = e0 + fel;
-    if (it < NITEM && fel < ne) {
-      const int d = face >> 1, side = face & 1;
-      const int nbe = neighbour(tb.nx, tb.ny, tb.nz, ee, d, side ? 1 : -1);
-      // the neighbour's face on the other side: its -d face for our +d face
-      const double* base = Qin + (int64_t)nbe * N3;
+    for (int f = 0; f < 5; ++f) hs[f * NH] = hb[f * EN3];
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  double nb[RNDG][5];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        const double* qn = base + f * EN3;
-        double v = 0.0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) v = fma(side ? lmr[m] : lpr[m], qn[tnode<N>(d, m, pt)], v);
-        nb[u][f] = v;
+  for (int u = 0; u < RNDG; ++u) {
+    const int s = wave + u * NW;
+    const int i = (s < S::NYZ ? S::chunk(s) : 0) * 64 + lane;
+    const int fel = i / N2, pt = i - fel * N2;
+    if (s < S::NYZ && i < FP && fel < ne) {
+      switch (S::face(s)) {   // uniform over the wave
+        case 2: chunk_trace<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+        case 3: chunk_trace<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+        case 4: chunk_trace<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+        default: chunk_trace<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
       }
     } else {
       nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;
@@ -161,29 +226,29 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
 
   // ---- B: Lax-Friedrichs flux at every face point
 #pragma unroll
-  for (int u = 0; u < IPT; ++u) {
-    const int it = tid + u * NT;
-    if (it < NITEM) {
-      const int face = it / FP;
-      const int rem = it - face * FP;
-      const int fel = rem / N2;
-      const int pt = rem - fel * N2;
-      const int d = face >> 1, side = face & 1;
-      double own[5], fs[5];
-      const double* coef = side ? sLp : sLm;
-#pragma unroll
-      for (int f = 0; f < 5; ++f) own[f] = line_trace<N>(sQ + f * NODES + fel * N3, coef, d, pt);
-      double qm[5], qp[5];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        qm[f] = side ? own[f] : nb[u][f];
-        qp[f] = side ? nb[u][f] : own[f];
+  for (int u = 0; u < RND; ++u) {
+    const int s = wave + u * NW;
+    const int i = (s < S::NS ? S::chunk(s) : 0) * 64 + lane;
+    if (s < S::NS && i < FP) {
+      const int face = S::face(s);
+      const int fel = i / N2, pt = i - fel * N2;
+      const double* own = sQ + (fel + 1) * N3;
+      const double* nbv = nb[u < RNDG ? u : 0];
+      const double g = tb.gamma, g1 = tb.gm1;
+      double fs[5];
+      switch (face) {   // uniform over the wave
+        case 0: face_flux<N, 0, 0, true>(own, own - N3, nbv, NH, pt, sLm, sLp, g, g1, fs); break;
+        case 1: face_flux<N, 0, 1, true>(own, own + N3, nbv, NH, pt, sLm, sLp, g, g1, fs); break;
+        case 2: face_flux<N, 1, 0, false>(own, own, nbv, NH, pt, sLm, sLp, g, g1, fs); break;
+        case 3: face_flux<N, 1, 1, false>(own, own, nbv, NH, pt, sLm, sLp, g, g1, fs); break;
+        case 4: face_flux<N, 2, 0, false>(own, own, nbv, NH, pt, sLm, sLp, g, g1, fs); break;
+        default: face_flux<N, 2, 1, false>(own, own, nbv, NH, pt, sLm, sLp, g, g1, fs); break;
       }
-      lf_flux(qm, qp, d, tb.gamma, tb.gm1, fs);
 #pragma unroll
-      for (int f = 0; f < 5; ++f) sH[(face * 5 + f) * FP + fel * N2 + pt] = fs[f];
+      for (int f = 0; f < 5; ++f) sH[(face * 5 + f) * FP + i] = fs[f];
     }
   }
+  __syncthreads();   // last reads of sQ; sF reuses it
 
   // ---- C: volume contraction + lift, one direction at a time
   const double rinv = 1.0 / q[0];
@@ -224,7 +289,7 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   if (MODE == 0) {
     if (act) {
 #pragma unroll
-      for (int f = 0; f < 5; ++f) st_stream(RR + f * EN3 + gofs, acc[f], nt);
+      for (int f = 0; f < 5; ++f) RR[f * EN3 + gofs] = acc[f];
     }
   } else {
 #pragma unroll
@@ -235,8 +300,8 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     if (act) {
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
-        st_stream(Qout + f * EN3 + gofs, q[f], nt);
-        st_stream(RR + f * EN3 + gofs, r[f], nt);
+        Qout[f * EN3 + gofs] = q[f];
+        RR[f * EN3 + gofs] = r[f];
       }
     }
   }

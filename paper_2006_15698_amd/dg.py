@@ -41,14 +41,12 @@ DG_OPT_XCD_REMAP = 2
 DG_OPT_ORDER = 3
 DG_OPT_PENCIL_X = 4
 DG_OPT_PENCIL_Z = 5
-DG_OPT_STREAM_STORES = 6
 DG_EXCHANGE_TRACES = 0
 DG_EXCHANGE_NEIGHBOUR = 1
 DG_ORDER_LINEAR = 0
 DG_ORDER_PENCIL = 1
 OPTION_NAMES = {DG_OPT_EXCHANGE: "exchange", DG_OPT_XCD_REMAP: "xcd_remap", DG_OPT_ORDER: "order",
-                DG_OPT_PENCIL_X: "pencil_x", DG_OPT_PENCIL_Z: "pencil_z",
-                DG_OPT_STREAM_STORES: "stream_stores"}
+                DG_OPT_PENCIL_X: "pencil_x", DG_OPT_PENCIL_Z: "pencil_z"}
 
 ERROR_NAMES = {DG_EINVAL: "DG_EINVAL", DG_EUNSUPPORTED: "DG_EUNSUPPORTED", DG_EHIP: "DG_EHIP",
                DG_EALIAS: "DG_EALIAS", DG_ENONPHYSICAL: "DG_ENONPHYSICAL",

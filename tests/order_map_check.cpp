@@ -1,8 +1,9 @@
 // Host check of the stage kernel's element-block visiting order
 // (dgdev::block_elements, compiled from the kernel's header): for every
 // mesh, pencil shape, block size and XCD setting below, each element is
-// covered by exactly one workgroup, blocks are non-empty and in range, and a
-// pencil-order block lies in one x-row.  Exit status 0 and "ok" on success.
+// covered by exactly one workgroup, blocks are non-empty, in range and lie
+// in one x-row, and the index order without XCD chunks visits blocks by
+// increasing first element.  Exit status 0 and "ok" on success.
 #include <cstdio>
 #include <vector>
 
@@ -21,6 +22,7 @@ static int check(int nx, int ny, int nz, int pencil_x, int pencil_z, int xcd) {
     unsigned grid;
     const DGOrder o = dg_order(&c, EPB, &grid);
     std::vector<int> hits(c.E, 0);
+    int last = -1;
     for (unsigned w = 0; w < grid; ++w) {
       int e0, ne;
       dgdev::block_elements<EPB>(tb, o, (int)w, (int)grid, e0, ne);
@@ -28,10 +30,15 @@ static int check(int nx, int ny, int nz, int pencil_x, int pencil_z, int xcd) {
         printf("block %u out of range: e0 %d ne %d\n", w, e0, ne);
         return 1;
       }
-      if (order == DG_ORDER_PENCIL && e0 / nx != (e0 + ne - 1) / nx) {
+      if (e0 / nx != (e0 + ne - 1) / nx) {
         printf("block %u leaves its row\n", w);
         return 1;
       }
+      if (order == DG_ORDER_LINEAR && !xcd && e0 <= last) {
+        printf("index order not increasing at block %u\n", w);
+        return 1;
+      }
+      last = e0;
       for (int k = 0; k < ne; ++k) hits[e0 + k]++;
     }
     for (int64_t e = 0; e < c.E; ++e)

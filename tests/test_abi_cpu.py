@@ -124,11 +124,10 @@ def test_options_validate_and_read_back(dg):
             with pytest.raises(dg.DGError):
                 dg.dg_set_option(ctx, key, bad)
             assert dg.dg_get_option(ctx, key) == good   # a rejected value changes nothing
-        for key in (dg.DG_OPT_XCD_REMAP, dg.DG_OPT_STREAM_STORES):
-            dg.dg_set_option(ctx, key, 5)
-            assert dg.dg_get_option(ctx, key) == 1
-            dg.dg_set_option(ctx, key, 0)
-            assert dg.dg_get_option(ctx, key) == 0
+        dg.dg_set_option(ctx, dg.DG_OPT_XCD_REMAP, 5)
+        assert dg.dg_get_option(ctx, dg.DG_OPT_XCD_REMAP) == 1
+        dg.dg_set_option(ctx, dg.DG_OPT_XCD_REMAP, 0)
+        assert dg.dg_get_option(ctx, dg.DG_OPT_XCD_REMAP) == 0
         with pytest.raises(dg.DGError):
             dg.dg_set_option(ctx, 99, 0)
         with pytest.raises(dg.DGError):

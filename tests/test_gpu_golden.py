@@ -1,0 +1,87 @@
+"""The 48^3 p = 4 Taylor-Green workload (one GPU's share at its real size)
+advanced 50 LSERK45 steps on the GPU, against the oracle's stored run
+(tests/golden/tgv48_p4_50steps.npz, written by make_tgv48_samples.py from
+the oracle alone): the state on 64 seeded elements, the domain integrals
+and the full-field L2 norms."""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tgv48_p4_50steps.npz")
+
+
+@pytest.fixture(scope="module")
+def golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden run not generated")
+    return dict(np.load(GOLDEN, allow_pickle=False))
+
+
+def _run(golden, precision):
+    import torch
+    from paper_2006_15698_amd import dg
+    L = (2 * math.pi,) * 3
+    s = dg.Solver((48,) * 3, 4, L=L, precision=precision)
+    Q0 = torch.from_numpy(W.tgv(48, 4)).cuda()
+    dt = float(golden["dt"])
+    assert abs(s.dt_cfl(Q0, 0.3) - dt) <= 1e-14 * dt
+    Q = Q0.clone()
+    res = torch.zeros_like(Q)
+    s.step(Q, res, dt, nsteps=int(golden["steps"]))
+    I = s.integrals(Q)
+    ex, ey, ez = golden["elems"].T
+    samp = Q[:, torch.from_numpy(ez).cuda(), torch.from_numpy(ey).cuda(), torch.from_numpy(ex).cuda()]
+    torch.cuda.synchronize()
+    return samp.cpu().numpy(), I, (Q0[:, torch.from_numpy(ez).cuda(), torch.from_numpy(ey).cuda(),
+                                      torch.from_numpy(ex).cuda()]).cpu().numpy()
+
+
+def _errors(golden, samp, samp0):
+    ref = golden["samples"]
+    d = np.abs(samp - ref).reshape(5, -1).max(axis=1)
+    m = np.abs(ref).reshape(5, -1).max(axis=1)
+    scale = np.array([m[0], m[1:4].max(), m[1:4].max(), m[1:4].max(), m[4]])
+    ch = np.abs(ref - samp0).reshape(5, -1).max(axis=1)
+    chs = np.array([ch[0], ch[1:4].max(), ch[1:4].max(), ch[1:4].max(), ch[4]])
+    l2 = np.sqrt(((samp - ref) ** 2).reshape(5, -1).sum(axis=1))
+    l2c = np.sqrt(((ref - samp0) ** 2).reshape(5, -1).sum(axis=1))
+    return d / scale, d / chs, l2 / l2c
+
+
+def test_tgv48_p4_fp64_50_steps(golden):
+    from paper_2006_15698_amd import dg
+    print("[golden tgv 48^3 p=4 fp64, 50 steps]", flush=True)
+    samp, I, samp0 = _run(golden, dg.DG_FP64)
+    rel_state, rel_change, l2_change = _errors(golden, samp, samp0)
+    print("state-relative", rel_state, "change-relative", rel_change, "L2 relative to change", l2_change)
+    assert np.all(rel_state <= 1e-12)
+    assert np.all(rel_change <= 1e-8)
+    I0, Io = golden["integrals0"], golden["integrals"]
+    # conserved integrals: both runs conserve to roundoff of the sums
+    scale = np.array([I0[0], I0[0], I0[0], I0[0], I0[4]])
+    assert np.all(np.abs(I[:5] - Io[:5]) <= 1e-13 * scale)
+    # kinetic energy: the inviscid flow changes it by only ~2e-10 of itself
+    # over these steps, less than the rounding of two different summation
+    # orders would allow to resolve; both sums agree to that rounding
+    print("kinetic energy: GPU", I[5], "oracle", Io[5], "change over the run", Io[5] - I0[5])
+    assert abs(I[5] - Io[5]) <= 1e-13 * abs(Io[5])
+
+
+def test_tgv48_p4_fp32_form_50_steps(golden):
+    """FP32 contractions against the FP64 oracle on the same run: the error
+    stays a small fraction of the 50-step change of the state."""
+    from paper_2006_15698_amd import dg
+    print("[golden tgv 48^3 p=4 fp32 form, 50 steps]", flush=True)
+    samp, I, samp0 = _run(golden, dg.DG_FP32_MFMA)
+    rel_state, rel_change, l2_change = _errors(golden, samp, samp0)
+    print("fp32 form: state-relative", rel_state, "change-relative", rel_change,
+          "L2 relative to change", l2_change)
+    assert np.all(rel_state <= 1e-7)
+    assert np.all(l2_change <= 1e-3)

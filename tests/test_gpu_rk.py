@@ -234,34 +234,38 @@ def test_exchange_schemes_bitwise_equal(dgm, p, prec):
 
 
 ORDER_SETTINGS = [
-    # (order, pencil_x, pencil_z, xcd_remap, stream_stores)
-    ("linear", 0, 1, 0, 0),
-    ("linear", 0, 1, 1, 1),
-    ("pencil", 0, 1, 0, 0),
-    ("pencil", 0, 2, 1, 0),
-    ("pencil", 3, 2, 1, 1),
-    ("pencil", 1, 40, 0, 1),
+    # (order, pencil_x, pencil_z, xcd_remap)
+    ("linear", 0, 1, 0),
+    ("linear", 0, 1, 1),
+    ("pencil", 0, 1, 0),
+    ("pencil", 0, 2, 1),
+    ("pencil", 3, 2, 1),
+    ("pencil", 1, 40, 0),
 ]
+
+
+def _set_order(dgm, s, order, px, pz, remap):
+    s.set_option(dgm.DG_OPT_ORDER, dgm.DG_ORDER_PENCIL if order == "pencil" else dgm.DG_ORDER_LINEAR)
+    s.set_option(dgm.DG_OPT_PENCIL_X, px)
+    s.set_option(dgm.DG_OPT_PENCIL_Z, pz)
+    s.set_option(dgm.DG_OPT_XCD_REMAP, remap)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("p,n", [(1, (7, 5, 3)), (2, (9, 2, 5)), (3, (6, 5, 7)), (4, (5, 3, 4)), (5, (3, 4, 5)),
-                                 (6, (2, 3, 3))])
+                                 (6, (2, 3, 3)), (7, (1, 2, 3))])
 def test_visiting_orders_bitwise_equal(dgm, p, n, prec):
-    """Every element-block visiting order and cache hint gives bit-identical
-    RHS and multi-stage results; x-extents that are not multiples of the
-    kernel's block leave short blocks at the row ends."""
+    """Every element-block visiting order gives bit-identical RHS and
+    multi-stage results; x-extents that are not multiples of the kernel's
+    block leave short blocks at the row ends, and a one-element row makes
+    an element its own x-neighbour."""
     import torch
     print(f"[visiting orders p={p} n={n} {prec}]", flush=True)
     Q0 = _dev(W.random_smooth(n, p, seed=110 + p, noise=0.02))
     outs = []
-    for order, px, pz, remap, nt in ORDER_SETTINGS:
+    for order, px, pz, remap in ORDER_SETTINGS:
         s = dgm.Solver(n, p, precision=dgm.DG_FP64 if prec == "fp64" else dgm.DG_FP32_MFMA)
-        s.set_option(dgm.DG_OPT_ORDER, dgm.DG_ORDER_PENCIL if order == "pencil" else dgm.DG_ORDER_LINEAR)
-        s.set_option(dgm.DG_OPT_PENCIL_X, px)
-        s.set_option(dgm.DG_OPT_PENCIL_Z, pz)
-        s.set_option(dgm.DG_OPT_XCD_REMAP, remap)
-        s.set_option(dgm.DG_OPT_STREAM_STORES, nt)
+        _set_order(dgm, s, order, px, pz, remap)
         dt = 0.2 * s.dt_cfl(Q0, 1.0)
         R = s.rhs(Q0)
         Q, res = Q0.clone(), torch.zeros_like(Q0)
@@ -275,19 +279,15 @@ def test_visiting_orders_bitwise_equal(dgm, p, n, prec):
 
 
 def test_visiting_orders_full_size_bitwise(dgm):
-    """Pencil order with XCD chunks and streaming hints at the 48^3 p=4 size:
-    bitwise equal to the linear order over a full step."""
+    """Pencil orders with and without XCD chunks at the 48^3 p=4 size:
+    bitwise equal to the index order over a full step."""
     import torch
     L = (2 * math.pi,) * 3
     Q0 = _dev(W.tgv(48, 4))
     outs = []
-    for order, px, pz, remap, nt in [("linear", 0, 1, 0, 0), ("pencil", 0, 6, 1, 1), ("pencil", 16, 8, 0, 0)]:
+    for order, px, pz, remap in [("linear", 0, 1, 0), ("pencil", 0, 6, 1), ("pencil", 16, 8, 0)]:
         s = dgm.Solver((48,) * 3, 4, L=L)
-        s.set_option(dgm.DG_OPT_ORDER, dgm.DG_ORDER_PENCIL if order == "pencil" else dgm.DG_ORDER_LINEAR)
-        s.set_option(dgm.DG_OPT_PENCIL_X, px)
-        s.set_option(dgm.DG_OPT_PENCIL_Z, pz)
-        s.set_option(dgm.DG_OPT_XCD_REMAP, remap)
-        s.set_option(dgm.DG_OPT_STREAM_STORES, nt)
+        _set_order(dgm, s, order, px, pz, remap)
         dt = s.dt_cfl(Q0, 0.3)
         Q, res = Q0.clone(), torch.zeros_like(Q0)
         s.step(Q, res, dt, nsteps=1)
