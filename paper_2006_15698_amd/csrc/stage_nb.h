@@ -157,13 +157,6 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   const int exl = x0 == 0 ? e0 + nx - 1 : e0 - 1;      // left neighbour of the block
   const int exr = x0 + ne == nx ? e0 - x0 : e0 + ne;    // right neighbour of the block
 
-  for (int x = tid; x < N * N; x += NT) sDh[x] = tb.Dh[x];
-  if (tid < N) {
-    sLm[tid] = tb.lm[tid];
-    sLp[tid] = tb.lp[tid];
-    sLiftm[tid] = tb.liftm[tid];
-    sLiftp[tid] = tb.liftp[tid];
-  }
   double lmr[N], lpr[N];             // l(-1), l(+1) in registers (kernarg tables)
 #pragma unroll
   for (int m = 0; m < N; ++m) {
@@ -171,38 +164,35 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     lpr[m] = tb.lp[m];
   }
 
-  // ---- A: own node and residual; block and x-neighbours into LDS;
-  //         y/z neighbour traces into registers
+  // ---- A: every global load of the block is issued before any is waited
+  //         for, in the order of use: own node, the x-neighbours' nodes,
+  //         the y/z neighbour traces (loads consumed by their FMA chains),
+  //         and last the residual, which stays in flight through the face
+  //         and volume phases (the load counter completes in order).
   const bool nthr = tid < NODES;
   const int el = tid / N3;
   const int t = tid - el * N3;
   const int ni = t % N, nj = (t / N) % N, nk = t / N2;
   const bool act = nthr && el < ne;
   const int64_t gofs = (int64_t)e0 * N3 + tid;
-  double q[5], r[5];
-  if (act) {
+  constexpr int HPT = (2 * N3 + NT - 1) / NT;   // x-neighbour nodes per thread
+  // Points of absent elements (and threads past the block's nodes) read the
+  // block's first node, a valid state whose results are never stored.  The
+  // loads are unconditional: a load under a condition is waited for where
+  // the branches join.
+  const int64_t lofs = act ? gofs : (int64_t)e0 * N3;
+  double q[5], r[5], hq[HPT][5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) q[f] = Qin[f * EN3 + gofs];
-  } else {
-    q[0] = 1.0; q[1] = 0.0; q[2] = 0.0; q[3] = 0.0; q[4] = 2.5;
-  }
+  for (int f = 0; f < 5; ++f) q[f] = Qin[f * EN3 + lofs];
 #pragma unroll
-  for (int f = 0; f < 5; ++f) r[f] = 0.0;
-  if (MODE != 0 && act && !first) {
+  for (int h = 0; h < HPT; ++h) {
+    const int x = tid + h * NT;
+    if (x < 2 * N3) {
+      const int right = x >= N3;
+      const double* hb = Qin + (int64_t)(right ? exr : exl) * N3 + (x - right * N3);
 #pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + gofs];
-  }
-  if (act) {   // slots past ne + 1 stay unwritten: only points of absent elements read them
-#pragma unroll
-    for (int f = 0; f < 5; ++f) sQ[f * NH + N3 + tid] = q[f];
-  }
-  for (int x = tid; x < 2 * N3; x += NT) {
-    const int right = x >= N3;
-    const int tt = x - right * N3;
-    const double* hb = Qin + (int64_t)(right ? exr : exl) * N3 + tt;
-    double* hs = sQ + (right ? ne + 1 : 0) * N3 + tt;
-#pragma unroll
-    for (int f = 0; f < 5; ++f) hs[f * NH] = hb[f * EN3];
+      for (int f = 0; f < 5; ++f) hq[h][f] = hb[f * EN3];
+    }
   }
   const int wave = tid >> 6, lane = tid & 63;
   double nb[RNDG][5];
@@ -220,6 +210,52 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
       }
     } else {
       nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;
+    }
+  }
+  // unconditional as well: the first stage reads the residual and ignores it
+  if (MODE != 0) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + lofs];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r[f] = 0.0;
+  }
+  // the 1-D tables, from uniform (scalar) kernarg reads: a per-thread
+  // vector read would be waited for behind the residual loads above
+  if (tid < N * N) {
+    double v = 0.0;
+#pragma unroll
+    for (int x = 0; x < N * N; ++x) v = tid == x ? tb.Dh[x] : v;
+    sDh[tid] = v;
+  }
+  if (tid < N) {
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      a = tid == m ? tb.lm[m] : a;
+      b = tid == m ? tb.lp[m] : b;
+      c = tid == m ? tb.liftm[m] : c;
+      d = tid == m ? tb.liftp[m] : d;
+    }
+    sLm[tid] = a;
+    sLp[tid] = b;
+    sLiftm[tid] = c;
+    sLiftp[tid] = d;
+  }
+  // stage the block (slots 1..ne) and its x-neighbours (slots 0 and ne + 1);
+  // slots past ne + 1 stay unwritten: only points of absent elements read them
+  if (act) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) sQ[f * NH + N3 + tid] = q[f];
+  }
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) {
+    const int x = tid + h * NT;
+    if (x < 2 * N3) {
+      const int right = x >= N3;
+      double* hs = sQ + (right ? ne + 1 : 0) * N3 + (x - right * N3);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) hs[f * NH] = hq[h][f];
     }
   }
   __syncthreads();
