@@ -12,6 +12,7 @@
 
 #include "dg_batch.h"
 #include "stage_fp32.h"
+#include "stage_nb32.h"
 #include "stage_fp64.h"
 #include "stage_nb.h"
 

@@ -4,6 +4,7 @@
 
 #include "dg_internal.h"
 #include "stage_fp32.h"
+#include "stage_nb32.h"
 #include "stage_nb.h"
 
 namespace {

@@ -24,7 +24,6 @@
 
 #include "dg_internal.h"
 #include "stage_fp64.h"
-#include "stage_nb.h"
 
 namespace dgdev {
 
@@ -385,250 +384,6 @@ __device__ __forceinline__ void stage_body32(const DGTables& tb, double* __restr
       }
       __syncthreads();
       write_traces32<N, EPB, NT>(sQ, sLm, sLp, e0, E, tout, tid);
-    }
-  }
-}
-
-// Shared-memory footprint (bytes) of the FP32 neighbour-read stage body.
-template <int N, int EPB>
-struct Nb32Smem {
-  static constexpr int NODES = EPB * N * N * N;
-  static constexpr int FP = EPB * N * N;
-  static constexpr int dbl = 5 * NODES + 30 * FP + 3 * N;   // sQ, sH, lift/rs tables
-  static constexpr int flt = 10 * NODES + N * N + 2 * N;     // sF, sV (one direction), Dh, l(+-1)
-  static constexpr int bytes = dbl * 8 + flt * 4;
-};
-
-// FP32 matrix-core stage with neighbour reads (Qin -> Qout, no trace
-// buffers).  A neighbour's trace is rebuilt exactly as the neighbour's own
-// launch rebuilds it (its FP64 anchor plus the FP32 deviation sum of
-// trace_dev), so both sides of a face see the same bits.  The volume
-// contraction runs one direction at a time: flux deviations of direction d
-// in sF, matrix-core products into sV, then the FP64 assembly.
-// Elements [e0, e0 + ne).  MODE 0: RR = dQ/dt.  MODE 1: RK stage (res = RR
-// in place).
-template <int N, int MODE, int EPB, int NT>
-__device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double* __restrict__ Qin,
-                                                double* __restrict__ Qout, double* __restrict__ RR, double rka,
-                                                double rkb, double dt, int first, int e0, int ne, double* smem,
-                                                int tid) {
-  constexpr int N2 = N * N, N3 = N2 * N;
-  constexpr int NODES = EPB * N3, FP = EPB * N2;
-  constexpr int NITEM = 6 * FP;
-  constexpr int IPT = (NITEM + NT - 1) / NT;
-  constexpr int NW = NT / 64;
-  constexpr int LINES = 5 * EPB * N2;       // 1-D lines per direction
-  constexpr int GD = (LINES + 15) / 16;     // matrix-core groups per direction
-  constexpr int GPW = (GD + NW - 1) / NW;   // groups per wave and direction
-  constexpr int KS = (N + 3) / 4;           // K steps of 4
-  static_assert(NODES <= NT, "one thread per node");
-  static_assert(NT % 64 == 0, "whole waves");
-
-  double* sQ = smem;                          // [5][NODES]
-  double* sH = sQ + 5 * NODES;                // [6][5][FP]
-  double* sLiftm = sH + 30 * FP;
-  double* sLiftp = sLiftm + N;
-  double* sRs = sLiftp + N;
-  float* sF = (float*)(sRs + N);              // [5][NODES] flux deviations of one direction
-  float* sV = sF + 5 * NODES;                 // [5][NODES] their contraction
-  float* sDh = sV + 5 * NODES;                // [N][N]
-  float* sLm = sDh + N * N;
-  float* sLp = sLm + N;
-
-  const int E = tb.E;
-  const int64_t EN3 = (int64_t)E * N3;
-
-  for (int x = tid; x < N * N; x += NT) sDh[x] = tb.Dh32[x];
-  if (tid < N) {
-    sLm[tid] = tb.lm32[tid];
-    sLp[tid] = tb.lp32[tid];
-    sLiftm[tid] = tb.liftm[tid];
-    sLiftp[tid] = tb.liftp[tid];
-    sRs[tid] = tb.rs[tid];
-  }
-  float lmr[N], lpr[N];
-#pragma unroll
-  for (int m = 0; m < N; ++m) {
-    lmr[m] = tb.lm32[m];
-    lpr[m] = tb.lp32[m];
-  }
-
-  // ---- A: node state, residual register, neighbour traces
-  const bool nthr = tid < NODES;
-  const int el = tid / N3;
-  const int t = tid - el * N3;
-  const int ni = t % N, nj = (t / N) % N, nk = t / N2;
-  const int e = e0 + el;
-  const bool act = nthr && el < ne;
-  const int64_t gofs = (int64_t)e * N3 + t;
-  double q[5], r[5];
-  if (act) {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) q[f] = Qin[f * EN3 + gofs];
-  } else {
-    q[0] = 1.0; q[1] = 0.0; q[2] = 0.0; q[3] = 0.0; q[4] = 2.5;
-  }
-#pragma unroll
-  for (int f = 0; f < 5; ++f) r[f] = 0.0;
-  if (MODE != 0 && act && !first) {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + gofs];
-  }
-  if (nthr) {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) sQ[f * NODES + tid] = q[f];
-  }
-  double nb[IPT][5];
-#pragma unroll
-  for (int u = 0; u < IPT; ++u) {
-    const int it = tid + u * NT;
-    const int face = it / FP;
-    const int rem = it - face * FP;
-    const int fel = rem / N2;
-    const int pt = rem - fel * N2;
-    const int ee = e0 + fel;
-    if (it < NITEM && fel < ne) {
-      const int d = face >> 1, side = face & 1;
-      const int nbe = neighbour(tb.nx, tb.ny, tb.nz, ee, d, side ? 1 : -1);
-      const double* base = Qin + (int64_t)nbe * N3;
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        const double* qn = base + f * EN3;
-        const double a = qn[0];
-        float v = 0.0f;
-#pragma unroll
-        for (int m = 0; m < N; ++m) v = fmaf(side ? lmr[m] : lpr[m], (float)(qn[tnode<N>(d, m, pt)] - a), v);
-        nb[u][f] = a + (double)v;
-      }
-    } else {
-      nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;
-    }
-  }
-  __syncthreads();
-
-  // ---- B: Lax-Friedrichs flux at every face point (FP64)
-#pragma unroll
-  for (int u = 0; u < IPT; ++u) {
-    const int it = tid + u * NT;
-    if (it < NITEM) {
-      const int face = it / FP;
-      const int rem = it - face * FP;
-      const int fel = rem / N2;
-      const int pt = rem - fel * N2;
-      const int d = face >> 1, side = face & 1;
-      const float* coef = side ? sLp : sLm;
-      double own[5], fs[5];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        const double* sq = sQ + f * NODES + fel * N3;
-        own[f] = sq[0] + (double)trace_dev<N>(sq, coef, d, pt, sq[0]);
-      }
-      double qm[5], qp[5];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        qm[f] = side ? own[f] : nb[u][f];
-        qp[f] = side ? nb[u][f] : own[f];
-      }
-      if (d == 0) lf_flux32_d<0>(qm, qp, tb.gamma, tb.gm1, fs);
-      else if (d == 1) lf_flux32_d<1>(qm, qp, tb.gamma, tb.gm1, fs);
-      else lf_flux32_d<2>(qm, qp, tb.gamma, tb.gm1, fs);
-#pragma unroll
-      for (int f = 0; f < 5; ++f) sH[(face * 5 + f) * FP + fel * N2 + pt] = fs[f];
-    }
-  }
-
-  // ---- C: per direction, matrix-core contraction of the flux deviations.
-  // v_mfma_f32_16x16x4_f32: A[i][k] from lane (i = l%16, k = l/16),
-  // B[k][j] from lane (k = l/16, j = l%16), D[i][j] in lane j = l%16,
-  // register r, row i = 4 (l/16) + r.  Rows i = output node index along
-  // the line, k = input node index a, columns j = 16 lines.
-  const int lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  float Areg[KS];
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int a = ks * 4 + lk;
-    Areg[ks] = (li < N && a < N) ? sDh[li * N + (a < N ? a : 0)] : 0.0f;
-  }
-  double aq[5];
-#pragma unroll
-  for (int f = 0; f < 5; ++f) aq[f] = sQ[f * NODES + el * N3];
-  double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double Fa[5];
-    if (d == 0) flux_dd<0>(aq, tb.gm1, Fa);
-    else if (d == 1) flux_dd<1>(aq, tb.gm1, Fa);
-    else flux_dd<2>(aq, tb.gm1, Fa);
-    if (nthr) {
-      double F[5];
-      if (d == 0) flux_dd<0>(q, tb.gm1, F);
-      else if (d == 1) flux_dd<1>(q, tb.gm1, F);
-      else flux_dd<2>(q, tb.gm1, F);
-#pragma unroll
-      for (int f = 0; f < 5; ++f) sF[f * NODES + tid] = (float)(F[f] - Fa[f]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int g = 0; g < GPW; ++g) {
-      const int gi = wave + g * NW;
-      if (gi < GD) {
-        const int line = gi * 16 + li;
-        const bool valid = line < LINES;
-        const int lf = valid ? line / (EPB * N2) : 0;
-        const int r2 = valid ? line - lf * (EPB * N2) : 0;
-        const int lel = r2 / N2;
-        const int lpt = r2 - lel * N2;
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const int a = ks * 4 + lk;
-          const float bv = (valid && a < N) ? sF[lf * NODES + lel * N3 + tnode<N>(d, a < N ? a : 0, lpt)] : 0.0f;
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Areg[ks], bv, acc, 0, 0, 0);
-        }
-        if (valid) {
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int i = 4 * lk + rr;
-            if (i < N) sV[lf * NODES + lel * N3 + tnode<N>(d, i, lpt)] = acc[rr];
-          }
-        }
-      }
-    }
-    __syncthreads();
-    if (nthr) {
-      const int m = d == 0 ? ni : (d == 1 ? nj : nk);
-      const int pt = d == 0 ? nj + N * nk : (d == 1 ? ni + N * nk : ni + N * nj);
-      const double sc = tb.sc[d];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        double s = (double)sV[f * NODES + tid];
-        s = fma(sRs[m], Fa[f], s);
-        s = fma(sLiftm[m], sH[((2 * d) * 5 + f) * FP + el * N2 + pt], s);
-        s = fma(-sLiftp[m], sH[((2 * d + 1) * 5 + f) * FP + el * N2 + pt], s);
-        acc5[f] = fma(sc, s, acc5[f]);
-      }
-    }
-  }
-
-  // ---- D: output
-  if (MODE == 0) {
-    if (act) {
-#pragma unroll
-      for (int f = 0; f < 5; ++f) RR[f * EN3 + gofs] = acc5[f];
-    }
-  } else {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      r[f] = first ? dt * acc5[f] : fma(rka, r[f], dt * acc5[f]);
-      q[f] = fma(rkb, r[f], q[f]);
-    }
-    if (act) {
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        Qout[f * EN3 + gofs] = q[f];
-        RR[f * EN3 + gofs] = r[f];
-      }
     }
   }
 }
