@@ -260,6 +260,7 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     value = dof * 5 * K / (ms * 1e-3) / 1e9
+    Qrun = Q.clone() if args.precision == "fp32" else None   # state after Wm + K steps
 
     out = {
         "metric": "GDOF-RK-stages/sec",
@@ -303,6 +304,30 @@ def main():
         out["fp64_rate"] = {"achieved_tflops": fl / avg_s / 1e12, "peak_tflops": FP64_PEAK_TFS,
                             "frac": fl / avg_s / 1e12 / FP64_PEAK_TFS,
                             "flops_per_dof_stage": flops_per_dof_stage(p + 1)}
+
+    if Qrun is not None:
+        # The FP32 form against the FP64 form on the same GPU: FP64 throughput
+        # measured the same way, and the L2 difference of the two states
+        # after the same Wm + K steps (the FP64 path equals the oracle to
+        # 1e-12 per RHS).
+        s64 = dg.Solver((n, n, n), p, L=L, precision=dg.DG_FP64)
+        Q64 = Q0.clone()
+        r64 = torch.zeros_like(Q64)
+        if Wm > 0:
+            s64.step(Q64, r64, dt, nsteps=Wm)
+        torch.cuda.synchronize()
+        ev0.record()
+        s64.step(Q64, r64, dt, nsteps=K)
+        ev1.record()
+        torch.cuda.synchronize()
+        v64 = dof * 5 * K / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+        diff = float(torch.linalg.vector_norm(Qrun - Q64))
+        out["fp32_vs_fp64"] = {
+            "speedup": value / v64, "fp64_value": v64, "steps_compared": Wm + K,
+            "l2_rel_diff": diff / float(torch.linalg.vector_norm(Q64)),
+            "l2_rel_diff_to_change": diff / float(torch.linalg.vector_norm(Q64 - Q0)),
+        }
+        del s64, Q64, r64
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, p, L, args.cpu_seconds)

@@ -1,9 +1,10 @@
 // Batched persistent kernels: many independent periodic meshes of uneven
 // size and polynomial degree advanced by one launch per RK stage.
 //
-// A work list of (mesh, first element) items, one item per block of up to EPB
-// consecutive elements of one x-row, is walked by a persistent grid (static round robin: item k
-// belongs to block k mod gridDim).  Each item runs the same fused
+// A work list of (mesh, first element) items, one item per block of up to
+// EPB consecutive elements of one x-row, is walked by a persistent grid
+// (static round robin: item k belongs to block k mod gridDim).  Each item
+// runs the same fused
 // neighbour-read stage body as the single-mesh kernel (stage_nb.h /
 // stage_fp32.h) with the compile-time degree N and elements-per-workgroup
 // EPB of its mesh, on a shared-memory buffer sized for the largest (N, EPB)
