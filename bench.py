@@ -36,6 +36,10 @@ WORKLOADS = {
                             "(one GPU's share at the paper's per-GPU size), 50 LSERK45 steps"),
     "tgv40_p6": (40, 6, 100, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 40^3 elements, p=6 "
                              "(the paper's degree), 100 LSERK45 steps"),
+    "adjoint16_p3": (16, 3, 40, "gradient of the integrated kinetic energy after 40 LSERK45 steps with respect to "
+                                "the initial state: perturbed Taylor-Green vortex (seed 1, amplitude 1e-2), 16^3 "
+                                "elements, p=3, dt from CFL 0.3, Q checkpointed every 8 steps; one bench step is "
+                                "one whole gradient (forward pass, recomputation and reverse pass)"),
     "batch512": (None, None, 20, "512 independent periodic meshes from seed 15698: density waves on "
                                  "[0,1]^3 and TGVs on [0,2pi]^3, n^3 elements with n uniform in 6..24, "
                                  "p uniform in 1..5, amplitudes uniform in [0.05,0.3], each mesh with "
@@ -107,6 +111,71 @@ def cpu_baseline(n, p, L, budget_s):
             "kind": "oracle",
             "sample": f"{stages} RK stages of the same workload ({dof} nodes) in {el:.1f} s; "
                       f"BLAS threads {threads}, host cpu_count {os.cpu_count()}"}
+
+
+def run_adjoint(args):
+    """The adjoint configuration: K whole gradients (forward 40 steps storing
+    Q every 8, then per segment recompute the stage inputs and run the stages
+    backwards through dg_rk_stage_vjp).  Rate: forward RK stages of the
+    gradient's trajectory per second.  Roofline of dg_rhs_vjp (one
+    neighbour-read adjoint launch, 120 algorithmic bytes per node: read Q and
+    gR, write gQ) from HIP events around each call, at this size and at TGV
+    32^3 p=3."""
+    import torch
+    import workloads as W
+    from paper_2006_15698_amd import dg
+
+    n, p, nsteps, desc = WORKLOADS["adjoint16_p3"]
+    K = 3 if args.steps is None else args.steps
+    L = (2 * math.pi,) * 3
+    s = dg.Solver((n, n, n), p, L=L)
+    Q0 = torch.from_numpy(W.perturbed_tgv(n, p, seed=1)).cuda()
+    dt = s.dt_cfl(Q0, 0.3)
+    grad = dg.kinetic_energy_grad(s)
+    for _ in range(max(args.warmup, 1)):
+        dg.rk_gradient(s, Q0, dt, nsteps, grad, every=8)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        g, _ = dg.rk_gradient(s, Q0, dt, nsteps, grad, every=8)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    dof = s.num_dof
+    value = dof * 5 * nsteps / (ms * 1e-3) / 1e9
+
+    def vjp_rate(solver, Q):
+        gR = torch.randn_like(Q)
+        out = torch.empty_like(Q)
+        for _ in range(3):
+            solver.rhs_vjp(Q, gR, out)
+        dg.dg_set_timing(solver.ctx, True)
+        for _ in range(20):
+            solver.rhs_vjp(Q, gR, out)
+        t = dg.dg_timing_read(solver.ctx)
+        dg.dg_set_timing(solver.ctx, False)
+        v_ms, v_n = t["vjp"]
+        avg_s = v_ms / v_n * 1e-3
+        nd = solver.num_dof
+        return avg_s, 120 * nd / avg_s / 1e9
+
+    avg16, gbs16 = vjp_rate(s, Q0)
+    s32 = dg.Solver((32,) * 3, 3, L=L)
+    avg32, gbs32 = vjp_rate(s32, torch.from_numpy(W.tgv(32, 3)).cuda())
+    return {
+        "metric": "GDOF-RK-stages/sec", "value": value, "unit": "GDOF-RK-stages/sec", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"adjoint16_p3: {desc}", "elements": n ** 3, "p": p, "dof": dof, "rk_steps": nsteps,
+                   "checkpoint_every": 8, "dt": dt},
+        "roofline": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_vjp_nb (dg_rhs_vjp) on TGV 32^3 p=3",
+                     "avg_launch_us": avg32 * 1e6, "alg_bytes_per_launch": 120 * s32.num_dof,
+                     "at_16p3": {"avg_launch_us": avg16 * 1e6, "achieved": gbs16}},
+    }
 
 
 def run_batch(args):
@@ -228,6 +297,9 @@ def main():
 
     if args.workload == "batch512":
         print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.workload == "adjoint16_p3":
+        print(json.dumps(run_adjoint(args)), flush=True)
         return
 
     n, p, cfg_steps, desc = WORKLOADS[args.workload]

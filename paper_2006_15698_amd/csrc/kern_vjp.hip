@@ -19,6 +19,7 @@
 // max(l-, l+) differentiates the - side when l- >= l+ (the forward's choice).
 
 #include "dg_internal.h"
+#include "stage_nb.h"
 
 namespace {
 
@@ -309,6 +310,276 @@ k_vjp(DGTables tb, const double* __restrict__ Q, const double* __restrict__ gR, 
   for (int f = 0; f < 5; ++f) gQ[f * EN3 + gofs] = acc[f];
 }
 
+// Neighbour-read adjoint: one launch, no trace buffers (the exchange of
+// the forward neighbour-read stage, stage_nb.h).  A workgroup owns EPB
+// consecutive elements of one x-row; the state Q and the adjoint gR of the
+// block and of its left and right x-neighbours are staged in LDS, the y/z
+// neighbours' traces of Q (l(-+1)) and lifted traces of gR (lift(-+1)) are
+// read by waves that each handle one face.  Same arithmetic as k_vtrace +
+// k_vjp (same FMA chains for every trace), so the results are bitwise equal.
+template <int N, int EPB>
+struct VjpSmem {
+  static constexpr int N3 = N * N * N;
+  static constexpr int NH = (EPB + 2) * N3;
+  static constexpr int FP = EPB * N * N;
+  static constexpr int size = 10 * NH + 30 * FP + N * N + 4 * N;
+};
+
+// Q trace (coefficients cq) and lifted gR trace (coefficients cg) of the
+// neighbour chunk element fel at point pt of our face (D, SIDE).
+template <int N, int D>
+__device__ __forceinline__ void chunk_trace2(const double* __restrict__ Q, const double* __restrict__ G, int64_t EN3,
+                                             int64_t cofs, int pt, const double* cq, const double* cg, double* qn,
+                                             double* gn) {
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double* qf = Q + f * EN3 + cofs;
+    const double* gf = G + f * EN3 + cofs;
+    double vq = 0.0, vg = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      vq = fma(cq[m], qf[vnode<N>(D, m, pt)], vq);
+      vg = fma(cg[m], gf[vnode<N>(D, m, pt)], vg);
+    }
+    qn[f] = vq;
+    gn[f] = vg;
+  }
+}
+
+// Adjoint of this element's side of face (D, SIDE) at point pt: own traces
+// from LDS (sQ, sG slot `so`), the neighbour's from LDS (slot `sn`, x-faces)
+// or from registers.
+template <int N, int D, int SIDE, bool LDSNB>
+__device__ __forceinline__ void face_vjp(const double* sQ, const double* sG, int so, int sn, const double* qnr,
+                                         const double* gnr, int NH, int pt, const double* sLm, const double* sLp,
+                                         const double* sLiftm, const double* sLiftp, double sc, double gamma,
+                                         double gm1, double* gq) {
+  constexpr int N3 = N * N * N;
+  double qo[5], go[5], qn[5], gn[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    qo[f] = line_sum<N>(sQ + f * NH + so * N3, SIDE ? sLp : sLm, D, pt);
+    go[f] = line_sum<N>(sG + f * NH + so * N3, SIDE ? sLiftp : sLiftm, D, pt);
+    qn[f] = LDSNB ? line_sum<N>(sQ + f * NH + sn * N3, SIDE ? sLm : sLp, D, pt) : qnr[f];
+    gn[f] = LDSNB ? line_sum<N>(sG + f * NH + sn * N3, SIDE ? sLiftm : sLiftp, D, pt) : gnr[f];
+  }
+  double gf[5], qm[5], qp[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    gf[f] = SIDE ? sc * (gn[f] - go[f]) : sc * (go[f] - gn[f]);
+    qm[f] = SIDE ? qo[f] : qn[f];
+    qp[f] = SIDE ? qn[f] : qo[f];
+  }
+  lf_vjp_d<D>(qm, qp, gamma, gm1, gf, SIDE != 0, gq);
+}
+
+template <int N>
+__global__ void __launch_bounds__(VCfg<N>::NT)
+k_vjp_nb(DGTables tb, const double* __restrict__ Q, const double* __restrict__ gR, double* __restrict__ gQ,
+         DGOrder ord) {
+  constexpr int EPB = VCfg<N>::EPB, NT = VCfg<N>::NT;
+  constexpr int N2 = N * N, N3 = N2 * N, NODES = EPB * N3, FP = EPB * N2, NH = (EPB + 2) * N3;
+  constexpr int NW = NT / 64;
+  using S = dgdev::FaceSlots<N, EPB>;
+  constexpr int RND = (S::NS + NW - 1) / NW;
+  constexpr int RNDG = (S::NYZ + NW - 1) / NW;
+  constexpr int HPT = (2 * N3 + NT - 1) / NT;
+  static_assert(NODES <= NT, "one thread per node");
+  __shared__ double smem[VjpSmem<N, EPB>::size];
+  double* sQ = smem;            // [5][NH] slot 0 left neighbour, 1..ne own, ne+1 right neighbour
+  double* sG = sQ + 5 * NH;     // [5][NH]
+  double* sH = sG + 5 * NH;     // [6][5][FP] face adjoints gq
+  double* sDh = sH + 30 * FP;
+  double* sLm = sDh + N * N;
+  double* sLp = sLm + N;
+  double* sLiftm = sLp + N;
+  double* sLiftp = sLiftm + N;
+
+  const int tid = threadIdx.x;
+  int e0, ne;
+  dgdev::block_elements<EPB>(tb, ord, blockIdx.x, gridDim.x, e0, ne);
+  const int nx = tb.nx, ny = tb.ny, nz = tb.nz;
+  const int64_t EN3 = (int64_t)tb.E * N3;
+  const int row = e0 / nx;
+  const int x0 = e0 - row * nx;
+  const int ey = row % ny, ez = row / ny;
+  const int plane = nx * ny;
+  const int eym = ey == 0 ? e0 + (ny - 1) * nx : e0 - nx;
+  const int eyp = ey == ny - 1 ? e0 - (ny - 1) * nx : e0 + nx;
+  const int ezm = ez == 0 ? e0 + (nz - 1) * plane : e0 - plane;
+  const int ezp = ez == nz - 1 ? e0 - (nz - 1) * plane : e0 + plane;
+  const int exl = x0 == 0 ? e0 + nx - 1 : e0 - 1;
+  const int exr = x0 + ne == nx ? e0 - x0 : e0 + ne;
+  double lmr[N], lpr[N], lfm[N], lfp[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    lmr[m] = tb.lm[m];
+    lpr[m] = tb.lp[m];
+    lfm[m] = tb.liftm[m];
+    lfp[m] = tb.liftp[m];
+  }
+
+  // ---- A: all loads before the first wait (unconditional; absent points
+  //         read the block's first node)
+  const bool nthr = tid < NODES;
+  const int el = tid / N3;
+  const int t = tid - el * N3;
+  const int ni = t % N, nj = (t / N) % N, nk = t / N2;
+  const bool act = nthr && el < ne;
+  const int64_t gofs = (int64_t)e0 * N3 + tid;
+  const int64_t lofs = act ? gofs : (int64_t)e0 * N3;
+  double q[5], g[5], hq[HPT][5], hg[HPT][5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    q[f] = Q[f * EN3 + lofs];
+    g[f] = gR[f * EN3 + lofs];
+  }
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) {
+    const int xh = tid + h * NT;
+    const int x = xh < 2 * N3 ? xh : 0;
+    const int right = x >= N3;
+    const int64_t hofs = (int64_t)(right ? exr : exl) * N3 + (x - right * N3);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      hq[h][f] = Q[f * EN3 + hofs];
+      hg[h][f] = gR[f * EN3 + hofs];
+    }
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  double qnb[RNDG][5], gnb[RNDG][5];
+#pragma unroll
+  for (int u = 0; u < RNDG; ++u) {
+    const int s = wave + u * NW;
+    const int i = (s < S::NYZ ? S::chunk(s) : 0) * 64 + lane;
+    const int fel = i / N2, pt = i - fel * N2;
+    if (s < S::NYZ && i < FP && fel < ne) {
+      switch (S::face(s)) {   // uniform over the wave; neighbour's face on the other side
+        case 2: chunk_trace2<N, 1>(Q, gR, EN3, (int64_t)(eym + fel) * N3, pt, lpr, lfp, qnb[u], gnb[u]); break;
+        case 3: chunk_trace2<N, 1>(Q, gR, EN3, (int64_t)(eyp + fel) * N3, pt, lmr, lfm, qnb[u], gnb[u]); break;
+        case 4: chunk_trace2<N, 2>(Q, gR, EN3, (int64_t)(ezm + fel) * N3, pt, lpr, lfp, qnb[u], gnb[u]); break;
+        default: chunk_trace2<N, 2>(Q, gR, EN3, (int64_t)(ezp + fel) * N3, pt, lmr, lfm, qnb[u], gnb[u]); break;
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        qnb[u][f] = f == 0 ? 1.0 : (f == 4 ? 2.5 : 0.0);
+        gnb[u][f] = 0.0;
+      }
+    }
+  }
+  // tables from uniform (scalar) kernarg reads
+  if (tid < N * N) {
+    double v = 0.0;
+#pragma unroll
+    for (int x = 0; x < N * N; ++x) v = tid == x ? tb.Dh[x] : v;
+    sDh[tid] = v;
+  }
+  if (tid < N) {
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      a = tid == m ? tb.lm[m] : a;
+      b = tid == m ? tb.lp[m] : b;
+      c = tid == m ? tb.liftm[m] : c;
+      d = tid == m ? tb.liftp[m] : d;
+    }
+    sLm[tid] = a;
+    sLp[tid] = b;
+    sLiftm[tid] = c;
+    sLiftp[tid] = d;
+  }
+  if (act) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      sQ[f * NH + N3 + tid] = q[f];
+      sG[f * NH + N3 + tid] = g[f];
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) {
+    const int x = tid + h * NT;
+    if (x < 2 * N3) {
+      const int right = x >= N3;
+      const int o = (right ? ne + 1 : 0) * N3 + (x - right * N3);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        sQ[f * NH + o] = hq[h][f];
+        sG[f * NH + o] = hg[h][f];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- B: adjoint of this element's side of every face
+#pragma unroll
+  for (int u = 0; u < RND; ++u) {
+    const int s = wave + u * NW;
+    const int i = (s < S::NS ? S::chunk(s) : 0) * 64 + lane;
+    if (s < S::NS && i < FP) {
+      const int face = S::face(s);
+      const int fel = i / N2, pt = i - fel * N2;
+      const int so = fel + 1;
+      const double* qv = qnb[u < RNDG ? u : 0];
+      const double* gv = gnb[u < RNDG ? u : 0];
+      const double ga = tb.gamma, g1 = tb.gm1;
+      double gq[5];
+      switch (face) {   // uniform over the wave
+        case 0:
+          face_vjp<N, 0, 0, true>(sQ, sG, so, so - 1, qv, gv, NH, pt, sLm, sLp, sLiftm, sLiftp, tb.sc[0], ga, g1, gq);
+          break;
+        case 1:
+          face_vjp<N, 0, 1, true>(sQ, sG, so, so + 1, qv, gv, NH, pt, sLm, sLp, sLiftm, sLiftp, tb.sc[0], ga, g1, gq);
+          break;
+        case 2:
+          face_vjp<N, 1, 0, false>(sQ, sG, so, so, qv, gv, NH, pt, sLm, sLp, sLiftm, sLiftp, tb.sc[1], ga, g1, gq);
+          break;
+        case 3:
+          face_vjp<N, 1, 1, false>(sQ, sG, so, so, qv, gv, NH, pt, sLm, sLp, sLiftm, sLiftp, tb.sc[1], ga, g1, gq);
+          break;
+        case 4:
+          face_vjp<N, 2, 0, false>(sQ, sG, so, so, qv, gv, NH, pt, sLm, sLp, sLiftm, sLiftp, tb.sc[2], ga, g1, gq);
+          break;
+        default:
+          face_vjp<N, 2, 1, false>(sQ, sG, so, so, qv, gv, NH, pt, sLm, sLp, sLiftm, sLiftp, tb.sc[2], ga, g1, gq);
+          break;
+      }
+#pragma unroll
+      for (int f = 0; f < 5; ++f) sH[(face * 5 + f) * FP + i] = gq[f];
+    }
+  }
+  __syncthreads();
+
+  // ---- C: volume (transposed contraction, flux Jacobian transpose) and the
+  //         face adjoints lifted back onto the lines
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int m = d == 0 ? ni : (d == 1 ? nj : nk);
+    const int pt = d == 0 ? nj + N * nk : (d == 1 ? ni + N * nk : ni + N * nj);
+    const double sc = tb.sc[d];
+    const double* gline = sG + (el + 1) * N3;
+    double gF[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int i2 = 0; i2 < N; ++i2) sacc = fma(sDh[i2 * N + m], gline[f * NH + vnode<N>(d, i2, pt)], sacc);
+      gF[f] = sc * sacc;
+    }
+    if (d == 0) flux_vjp<0>(q, gF, tb.gm1, acc);
+    else if (d == 1) flux_vjp<1>(q, gF, tb.gm1, acc);
+    else flux_vjp<2>(q, gF, tb.gm1, acc);
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+      acc[f] += sLp[m] * sH[((2 * d + 1) * 5 + f) * FP + el * N2 + pt] + sLm[m] * sH[((2 * d) * 5 + f) * FP + el * N2 + pt];
+  }
+  if (act) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) gQ[f * EN3 + gofs] = acc[f];
+  }
+}
+
 // gtot = gres + b * gQ (state-sized axpy for the reverse RK stage).
 __global__ void __launch_bounds__(256)
 k_axpy(int64_t n, const double* __restrict__ x, double b, const double* __restrict__ y, double* __restrict__ out) {
@@ -337,9 +608,30 @@ int launch_vjp_n(const dg_ctx* c, const double* Q, const double* gR, double* gQ,
   return (int)hipGetLastError();
 }
 
+template <int N>
+int launch_vjp_nb_n(const dg_ctx* c, const double* Q, const double* gR, double* gQ) {
+  unsigned grid;
+  const DGOrder ord = dg_order(c, VCfg<N>::EPB, &grid);
+  hipLaunchKernelGGL(k_vjp_nb<N>, dim3(grid), dim3(VCfg<N>::NT), 0, c->stream, c->tab, Q, gR, gQ, ord);
+  return (int)hipGetLastError();
+}
+
 }  // namespace
 
 int dg_launch_vjp(const dg_ctx* c, const double* Q, const double* gR, double* gQ, char* ws) {
+  if (c->exchange == DG_EXCHANGE_NEIGHBOUR) {
+    switch (c->N) {
+      case 1: return launch_vjp_nb_n<1>(c, Q, gR, gQ);
+      case 2: return launch_vjp_nb_n<2>(c, Q, gR, gQ);
+      case 3: return launch_vjp_nb_n<3>(c, Q, gR, gQ);
+      case 4: return launch_vjp_nb_n<4>(c, Q, gR, gQ);
+      case 5: return launch_vjp_nb_n<5>(c, Q, gR, gQ);
+      case 6: return launch_vjp_nb_n<6>(c, Q, gR, gQ);
+      case 7: return launch_vjp_nb_n<7>(c, Q, gR, gQ);
+      case 8: return launch_vjp_nb_n<8>(c, Q, gR, gQ);
+      default: return (int)hipErrorInvalidValue;
+    }
+  }
   const DGWorkspace L = dg_workspace_layout(c);
   double* TQ = (double*)(ws + L.off_trace0);
   double* TG = (double*)(ws + L.off_trace1);

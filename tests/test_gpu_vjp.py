@@ -179,3 +179,30 @@ def test_checkpointing_interval_does_not_change_gradient(dgm):
     g12, _ = dgm.rk_gradient(s, Q0, dt, 12, fg, every=12)
     torch.cuda.synchronize()
     assert torch.equal(g1, g8) and torch.equal(g8, g12)
+
+
+@pytest.mark.parametrize("p,n", [(1, (7, 5, 3)), (2, (9, 2, 5)), (3, (6, 5, 7)), (4, (5, 3, 4)), (5, (3, 4, 5)),
+                                 (6, (2, 3, 3)), (7, (1, 2, 3))])
+def test_vjp_exchange_schemes_and_orders_bitwise_equal(dgm, p, n):
+    """The neighbour-read adjoint (one launch) equals the trace-buffer adjoint
+    (trace launches + VJP launch) bit for bit, for every visiting order, on
+    ragged meshes (short row blocks, a one-element row)."""
+    import torch
+    print(f"[vjp schemes p={p} n={n}]", flush=True)
+    Q = _dev(W.random_smooth(n, p, seed=130 + p, noise=0.05))
+    V = torch.randn_like(Q)
+    outs = []
+    for exch, order, px, pz, remap in [(dgm.DG_EXCHANGE_TRACES, dgm.DG_ORDER_LINEAR, 0, 1, 0),
+                                       (dgm.DG_EXCHANGE_NEIGHBOUR, dgm.DG_ORDER_LINEAR, 0, 1, 0),
+                                       (dgm.DG_EXCHANGE_NEIGHBOUR, dgm.DG_ORDER_PENCIL, 3, 2, 1),
+                                       (dgm.DG_EXCHANGE_NEIGHBOUR, dgm.DG_ORDER_PENCIL, 0, 40, 0)]:
+        s = dgm.Solver(n, p)
+        s.set_option(dgm.DG_OPT_EXCHANGE, exch)
+        s.set_option(dgm.DG_OPT_ORDER, order)
+        s.set_option(dgm.DG_OPT_PENCIL_X, px)
+        s.set_option(dgm.DG_OPT_PENCIL_Z, pz)
+        s.set_option(dgm.DG_OPT_XCD_REMAP, remap)
+        outs.append(s.rhs_vjp(Q, V))
+        torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch.equal(outs[0], o)
