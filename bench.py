@@ -259,6 +259,9 @@ def main():
                     help="element-block visiting order of the stage kernel (default: library's)")
     ap.add_argument("--pencil-x", type=int, default=None, help="pencil extent along x in elements (0: row)")
     ap.add_argument("--pencil-z", type=int, default=None, help="pencil extent along z in element planes")
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
+                    help="1: advance the timed steps by replaying captured HIP graphs (dg_rk_graph_steps); "
+                         "measured no faster than direct launches at these sizes, so off by default")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, time a plain device-to-device copy of MIB MiB "
                          "(calibrates HBM byte counters; reports the copy bandwidth)")
@@ -321,13 +324,14 @@ def main():
     dt = s.dt_cfl(Q0, 0.3)
     Q = Q0.clone()
     res = torch.zeros_like(Q)
+    graph = bool(args.graph)
     if Wm > 0:
-        s.step(Q, res, dt, nsteps=Wm)
+        s.step(Q, res, dt, nsteps=Wm, graph=graph)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    s.step(Q, res, dt, nsteps=K)
+    s.step(Q, res, dt, nsteps=K, graph=graph)
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
@@ -349,7 +353,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "elements": n ** 3, "p": p,
                    "dof": dof, "precision": args.precision, "dt": dt,
-                   "options": s.options()},
+                   "options": s.options(), "graph_replay": graph},
     }
 
     if not args.no_roofline:
@@ -386,10 +390,10 @@ def main():
         Q64 = Q0.clone()
         r64 = torch.zeros_like(Q64)
         if Wm > 0:
-            s64.step(Q64, r64, dt, nsteps=Wm)
+            s64.step(Q64, r64, dt, nsteps=Wm, graph=graph)
         torch.cuda.synchronize()
         ev0.record()
-        s64.step(Q64, r64, dt, nsteps=K)
+        s64.step(Q64, r64, dt, nsteps=K, graph=graph)
         ev1.record()
         torch.cuda.synchronize()
         v64 = dof * 5 * K / (ev0.elapsed_time(ev1) * 1e-3) / 1e9

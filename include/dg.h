@@ -171,6 +171,15 @@ int dg_rk_step(dg_ctx* ctx, double* Q, double* res, double dt);
  * dg_rk_step. */
 int dg_rk_steps(dg_ctx* ctx, double* Q, double* res, double dt, int nsteps);
 
+/* As dg_rk_steps (bitwise the same result), with each step's five stage
+ * launches captured once in a HIP graph (one per ping-pong parity of the
+ * neighbour-read exchange) and replayed nsteps times on an internal stream
+ * that is ordered after, and before, the context's stream by events.  The
+ * graphs are kept while Q, res, dt and the context's settings stay the
+ * same, and rebuilt otherwise.  Launches inside the graphs are not seen by
+ * dg_set_timing.  With DG_EXCHANGE_TRACES it runs as dg_rk_steps. */
+int dg_rk_graph_steps(dg_ctx* ctx, double* Q, double* res, double dt, int nsteps);
+
 /* Vector-Jacobian product of the right-hand side: gQ = (dR/dQ)^T gR at Q,
  * FP64, overwriting gQ.  At the kinks of max and |.| in the face flux the
  * branch taken by the forward evaluation is differentiated (ties: the -

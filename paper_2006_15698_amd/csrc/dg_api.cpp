@@ -364,6 +364,13 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
   c->xcd_remap = 1;
   c->pencil_x = 16;
   c->pencil_z = 8;
+  c->epoch = 1;
+  c->gstream = nullptr;
+  c->ev_in = c->ev_out = nullptr;
+  c->gexec[0] = c->gexec[1] = nullptr;
+  c->gQ = c->gR = nullptr;
+  c->gdt = 0.0;
+  c->gepoch = 0;
   build_tables(c);
   g_err[0] = 0;
   return c;
@@ -372,6 +379,11 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
 void dg_destroy(dg_ctx* c) {
   if (!c) return;
   delete (DGTiming*)c->timing;
+  for (int k = 0; k < 2; ++k)
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   delete c;
 }
 
@@ -415,6 +427,7 @@ int dg_set_domain(dg_ctx* c, double Lx, double Ly, double Lz) {
   c->L[1] = Ly;
   c->L[2] = Lz;
   build_tables(c);
+  ++c->epoch;
   return DG_OK;
 }
 
@@ -428,11 +441,13 @@ int dg_set_precision(dg_ctx* c, int mode) {
   if (!c) return fail(DG_EINVAL, "NULL context");
   if (mode == DG_FP64) {
     c->precision = mode;
+    ++c->epoch;
     return DG_OK;
   }
   if (mode == DG_FP32_MFMA) {
     if (!dg_f32_supported(c->N)) return fail(DG_EUNSUPPORTED, "FP32 matrix-core form not built for p=%d", c->p);
     c->precision = mode;
+    ++c->epoch;
     return DG_OK;
   }
   return fail(DG_EINVAL, "unknown precision mode %d", mode);
@@ -444,25 +459,30 @@ int dg_set_option(dg_ctx* c, int key, int value) {
     if (value != DG_EXCHANGE_TRACES && value != DG_EXCHANGE_NEIGHBOUR)
       return fail(DG_EINVAL, "unknown exchange %d", value);
     c->exchange = value;
+    ++c->epoch;
     return DG_OK;
   }
   if (key == DG_OPT_XCD_REMAP) {
     c->xcd_remap = value ? 1 : 0;
+    ++c->epoch;
     return DG_OK;
   }
   if (key == DG_OPT_ORDER) {
     if (value != DG_ORDER_LINEAR && value != DG_ORDER_PENCIL) return fail(DG_EINVAL, "unknown order %d", value);
     c->order = value;
+    ++c->epoch;
     return DG_OK;
   }
   if (key == DG_OPT_PENCIL_X) {
     if (value < 0) return fail(DG_EINVAL, "pencil x extent %d < 0", value);
     c->pencil_x = value;
+    ++c->epoch;
     return DG_OK;
   }
   if (key == DG_OPT_PENCIL_Z) {
     if (value < 1) return fail(DG_EINVAL, "pencil z extent %d < 1", value);
     c->pencil_z = value;
+    ++c->epoch;
     return DG_OK;
   }
   return fail(DG_EINVAL, "unknown option %d", key);
@@ -493,6 +513,7 @@ int dg_set_workspace(dg_ctx* c, void* dptr, size_t bytes) {
   if (bytes < need) return fail(DG_EWORKSPACE, "workspace %zu bytes < %zu", bytes, need);
   c->ws = (char*)dptr;
   c->ws_bytes = bytes;
+  ++c->epoch;
   return DG_OK;
 }
 
@@ -556,6 +577,82 @@ int dg_rk_steps(dg_ctx* c, double* Q, double* res, double dt, int nsteps) {
 }
 
 int dg_rk_step(dg_ctx* c, double* Q, double* res, double dt) { return dg_rk_steps(c, Q, res, dt, 1); }
+
+int dg_rk_graph_steps(dg_ctx* c, double* Q, double* res, double dt, int nsteps) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  rc = check_state_pair(c, Q, "Q", res, "res");
+  if (rc) return rc;
+  if (nsteps == 0) return DG_OK;
+  if (c->exchange != DG_EXCHANGE_NEIGHBOUR) return stages(c, Q, res, dt, 0, 5 * nsteps);
+  int err;
+  if (!c->gstream) {
+    err = (int)hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking);
+    if (err) return hip_fail(err, "graph stream");
+    err = (int)hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+    if (err) return hip_fail(err, "graph event");
+    err = (int)hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+    if (err) return hip_fail(err, "graph event");
+  }
+  if (c->gQ != Q || c->gR != res || c->gdt != dt || c->gepoch != c->epoch) {
+    for (int k = 0; k < 2; ++k) {
+      if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+      c->gexec[k] = nullptr;
+    }
+  }
+  // the graph stream runs after the caller's stream, and the caller's
+  // stream after it
+  err = (int)hipEventRecord(c->ev_in, c->stream);
+  if (err) return hip_fail(err, "event record");
+  err = (int)hipStreamWaitEvent(c->gstream, c->ev_in, 0);
+  if (err) return hip_fail(err, "stream wait");
+  double* buf[2] = {Q, q2_buf(c)};
+  for (int par = 0; par < 2; ++par) {
+    if (c->gexec[par]) continue;
+    // one step = five stage launches; a step that starts from buf[par]
+    // (stage count before it of parity par) alternates from there
+    hipGraph_t graph = nullptr;
+    const hipStream_t user = c->stream;
+    c->stream = c->gstream;
+    err = (int)hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    int lerr = 0;
+    for (int s = 0; s < 5 && !err && !lerr; ++s) {
+      const int g = par + s;
+      lerr = c->precision == DG_FP32_MFMA
+                 ? dg_launch_stage_nb_f32(c, buf[g & 1], buf[(g + 1) & 1], res, 1, kRKA[s], kRKB[s], dt, s == 0)
+                 : dg_launch_stage_nb(c, buf[g & 1], buf[(g + 1) & 1], res, 1, kRKA[s], kRKB[s], dt, s == 0);
+    }
+    const int cerr = err ? err : (int)hipStreamEndCapture(c->gstream, &graph);
+    c->stream = user;
+    if (err) return hip_fail(err, "begin capture");
+    if (lerr || cerr) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(lerr ? lerr : cerr, "capture");
+    }
+    err = (int)hipGraphInstantiate(&c->gexec[par], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (err) return hip_fail(err, "graph instantiate");
+  }
+  c->gQ = Q;
+  c->gR = res;
+  c->gdt = dt;
+  c->gepoch = c->epoch;
+  for (int n = 0; n < nsteps; ++n) {
+    err = (int)hipGraphLaunch(c->gexec[n & 1], c->gstream);
+    if (err) return hip_fail(err, "graph launch");
+  }
+  if (nsteps & 1) {
+    err = (int)hipMemcpyAsync(Q, buf[1], state_bytes(c), hipMemcpyDeviceToDevice, c->gstream);
+    if (err) return hip_fail(err, "state copy");
+  }
+  err = (int)hipEventRecord(c->ev_out, c->gstream);
+  if (err) return hip_fail(err, "event record");
+  err = (int)hipStreamWaitEvent(c->stream, c->ev_out, 0);
+  if (err) return hip_fail(err, "stream wait");
+  return DG_OK;
+}
 
 int dg_rhs_vjp(dg_ctx* c, const double* Q, const double* gR, double* gQ) {
   int rc = check_ready(c);

@@ -52,6 +52,17 @@ struct dg_ctx {
   int order;      // DG_ORDER_LINEAR or DG_ORDER_PENCIL
   int pencil_x;   // pencil extent along x in elements (0: whole row)
   int pencil_z;   // pencil extent along z in element planes
+  // graph replay of whole steps (dg_rk_graph_steps): one executable graph
+  // per ping-pong parity, valid while the arrays, dt and `epoch` (bumped by
+  // every setter that changes what a launch does) are unchanged
+  unsigned epoch;
+  hipStream_t gstream;
+  hipEvent_t ev_in, ev_out;
+  hipGraphExec_t gexec[2];
+  const double* gQ;
+  const double* gR;
+  double gdt;
+  unsigned gepoch;
 };
 
 // Order in which a neighbour-read stage launch visits its element blocks

@@ -70,6 +70,7 @@ _SIGS = {
     "dg_rk_stage": (_i, [_vp, _i, _vp, _vp, _d]),
     "dg_rk_step": (_i, [_vp, _vp, _vp, _d]),
     "dg_rk_steps": (_i, [_vp, _vp, _vp, _d, _i]),
+    "dg_rk_graph_steps": (_i, [_vp, _vp, _vp, _d, _i]),
     "dg_rhs_vjp": (_i, [_vp, _vp, _vp, _vp]),
     "dg_rk_stage_vjp": (_i, [_vp, _i, _vp, _vp, _vp, _d]),
     "dg_integrals": (_i, [_vp, _vp, _dp]),
@@ -224,6 +225,11 @@ def dg_rk_step(ctx, Q, res, dt):
 def dg_rk_steps(ctx, Q, res, dt, nsteps):
     nd = _nd(ctx)
     return _check(_lib.dg_rk_steps(ctx, _ptr(Q, nd), _ptr(res, nd), float(dt), int(nsteps)))
+
+
+def dg_rk_graph_steps(ctx, Q, res, dt, nsteps):
+    nd = _nd(ctx)
+    return _check(_lib.dg_rk_graph_steps(ctx, _ptr(Q, nd), _ptr(res, nd), float(dt), int(nsteps)))
 
 
 def dg_rhs_vjp(ctx, Q, gR, gQ):
@@ -477,9 +483,14 @@ class Solver:
         self._s()
         dg_rk_stage(self.ctx, s, Q, res, dt)
 
-    def step(self, Q, res, dt, nsteps=1):
+    def step(self, Q, res, dt, nsteps=1, graph=False):
+        """nsteps LSERK45 steps in place; graph=True replays captured
+        steps (dg_rk_graph_steps), bitwise the same result."""
         self._s()
-        dg_rk_steps(self.ctx, Q, res, dt, nsteps)
+        if graph:
+            dg_rk_graph_steps(self.ctx, Q, res, dt, nsteps)
+        else:
+            dg_rk_steps(self.ctx, Q, res, dt, nsteps)
 
     def rhs_vjp(self, Q, gR, out=None):
         out = self.empty() if out is None else out

@@ -297,3 +297,28 @@ def test_visiting_orders_full_size_bitwise(dgm):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_steps_bitwise_equal_every_replay(dgm, prec):
+    """Graph-replayed steps equal eager steps bit for bit, on every replay,
+    with the program's own eager work and synchronisations in between, odd
+    and even step counts (the ping-pong copy-back), and after a setting
+    change (the graphs are rebuilt)."""
+    import torch
+    n, p = (6, 5, 7), 3
+    s = dgm.Solver(n, p, precision=dgm.DG_FP64 if prec == "fp64" else dgm.DG_FP32_MFMA)
+    Q0 = _dev(W.random_smooth(n, p, seed=140, noise=0.02))
+    dt = 0.2 * s.dt_cfl(Q0, 1.0)
+    Qe, re = Q0.clone(), torch.zeros_like(Q0)
+    Qg, rg = Q0.clone(), torch.zeros_like(Q0)
+    for k, ns in enumerate([3, 2, 1, 4, 1]):
+        if k == 3:
+            s.set_option(dgm.DG_OPT_PENCIL_Z, 2)   # changes the launches: graphs rebuilt
+        s.step(Qe, re, dt, nsteps=ns)
+        torch.cuda.synchronize()
+        junk = (Qe * 2.0).sum()                    # eager work between replays
+        s.step(Qg, rg, dt, nsteps=ns, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(Qe, Qg) and torch.equal(re, rg), (k, ns)
+        del junk
