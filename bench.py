@@ -55,12 +55,20 @@ def flops_per_dof_stage(N):
     return 38 + 30 * N + 3 * (40 * N + 76) / N + 30
 
 
+# The sources the measured stage kernels are built from (FP64 and FP32
+# neighbour-read forms, their tables and launch parameters).
+STAGE_SOURCES = ["include/dg.h", "paper_2006_15698_amd/csrc/dg_internal.h",
+                 "paper_2006_15698_amd/csrc/stage_fp64.h", "paper_2006_15698_amd/csrc/stage_nb.h",
+                 "paper_2006_15698_amd/csrc/kern_fp64.hip", "paper_2006_15698_amd/csrc/stage_fp32.h",
+                 "paper_2006_15698_amd/csrc/stage_nb32.h", "paper_2006_15698_amd/csrc/kern_fp32.hip"]
+
+
 def kernel_source_hash():
-    """Hash of every kernel source: counters taken on other sources are stale."""
+    """Hash of the stage kernels' sources: counters taken on other sources
+    are stale."""
     h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2006_15698_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
