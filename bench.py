@@ -63,13 +63,22 @@ STAGE_SOURCES = ["include/dg.h", "paper_2006_15698_amd/csrc/dg_internal.h",
                  "paper_2006_15698_amd/csrc/stage_nb32.h", "paper_2006_15698_amd/csrc/kern_fp32.hip"]
 
 
+def _code_only(text):
+    """Source text without comments and blank space, so that editing a
+    comment does not mark counters stale."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
-    """Hash of the stage kernels' sources: counters taken on other sources
-    are stale."""
+    """Hash of the stage kernels' code: counters taken on other code are
+    stale."""
     h = hashlib.sha256()
     for f in STAGE_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -6,7 +6,7 @@
 // (static round robin: item k belongs to block k mod gridDim).  Each item
 // runs the same fused
 // neighbour-read stage body as the single-mesh kernel (stage_nb.h /
-// stage_fp32.h) with the compile-time degree N and elements-per-workgroup
+// stage_nb32.h) with the compile-time degree N and elements-per-workgroup
 // EPB of its mesh, on a shared-memory buffer sized for the largest (N, EPB)
 // variant.  Every variant uses 256 threads.  The state of all meshes
 // alternates between two buffers (Qin -> Qout) from launch to launch.

@@ -1,6 +1,8 @@
-// Single-mesh kernels of the FP32 matrix-core variant (device code in
-// stage_fp32.h): face traces as FP32 deviations plus FP64 anchors, and the
-// fused stage with the volume contractions on v_mfma_f32_16x16x4_f32.
+// Single-mesh kernels of the FP32 matrix-core variant: the fused stage with
+// the volume contractions on v_mfma_f32_16x16x4_f32, either reading the
+// neighbours' states in the same launch (k_stage_nb32, stage_nb32.h, the
+// default) or exchanging face traces as FP32 deviations plus FP64 anchors
+// between launches (stage_fp32.h).
 
 #include "dg_internal.h"
 #include "stage_fp32.h"

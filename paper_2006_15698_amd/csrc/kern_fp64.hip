@@ -1,11 +1,18 @@
 // FP64 kernels of the DG Euler right-hand side and the LSERK45 stage update
-// for gfx950 (device code of the stage in stage_fp64.h).
+// for gfx950.
 //
-// Per RK stage one launch of k_stage: flux, local Lax-Friedrichs face flux,
-// sum-factorised volume contraction and lift, RK axpy, and the face traces
-// of the updated state for the next launch.  HBM traffic per node and stage:
-// Q and res read and written once (160 B) plus the face traces
-// (2 * 6 N^2 * 5 * 8 B per element).  The tree reductions below give
+// Per RK stage one launch does the pointwise flux, the local Lax-Friedrichs
+// face flux, the sum-factorised volume contraction and lift, and the RK
+// axpy.  Two ways to obtain a neighbour's state on a shared face:
+//   k_stage_nb (stage_nb.h, the default): the neighbour's trace is
+//     interpolated from its state in the same launch; the state alternates
+//     between two buffers (Qin -> Qout).  HBM traffic per node and stage:
+//     Q and res read and written once (160 B) plus neighbour reads that
+//     miss the caches.
+//   k_stage (stage_fp64.h): each launch also writes the face traces of the
+//     updated state, which the next launch reads: 160 B plus
+//     2 * 6 N^2 * 5 * 8 B per element.
+// Both give bitwise the same results.  The tree reductions below give
 // integrals, the maximum wave rate and the state check in a fixed order.
 
 #include "dg_internal.h"

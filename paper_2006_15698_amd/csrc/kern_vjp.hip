@@ -9,7 +9,9 @@
 // Reverse mode, per element (no atomics: each side of a face computes the
 // adjoint of its own trace):
 //   1. lifted adjoint traces G_{e,+-d}(pt) = sum_m lift+-[m] gR_e(line) and
-//      forward traces T of Q, exchanged between neighbours through HBM;
+//      forward traces T of Q, of this element and of its neighbours (read
+//      from the neighbours' Q and gR in the same launch by k_vjp_nb, or
+//      exchanged through trace buffers by k_vtrace + k_vjp);
 //   2. face flux adjoint gF*_{face} = (2/h_d)(G_{plus elem,-d} - G_{minus elem,+d}),
 //      then the LF Jacobian transpose for this element's side, then the
 //      trace transpose l_m(+-1) back onto the line;
