@@ -55,12 +55,15 @@ def flops_per_dof_stage(N):
     return 38 + 30 * N + 3 * (40 * N + 76) / N + 30
 
 
-# The sources the measured stage kernels are built from (FP64 and FP32
-# neighbour-read forms, their tables and launch parameters).
-STAGE_SOURCES = ["include/dg.h", "paper_2006_15698_amd/csrc/dg_internal.h",
-                 "paper_2006_15698_amd/csrc/stage_fp64.h", "paper_2006_15698_amd/csrc/stage_nb.h",
-                 "paper_2006_15698_amd/csrc/kern_fp64.hip", "paper_2006_15698_amd/csrc/stage_fp32.h",
-                 "paper_2006_15698_amd/csrc/stage_nb32.h", "paper_2006_15698_amd/csrc/kern_fp32.hip"]
+# The sources each measured stage kernel is built from (neighbour-read form,
+# its tables and launch parameters), per precision.
+_COMMON_SOURCES = ["include/dg.h", "paper_2006_15698_amd/csrc/dg_internal.h",
+                   "paper_2006_15698_amd/csrc/stage_fp64.h", "paper_2006_15698_amd/csrc/stage_nb.h"]
+STAGE_SOURCES = {
+    "fp64": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_fp64.hip"],
+    "fp32": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/stage_fp32.h", "paper_2006_15698_amd/csrc/stage_nb32.h",
+                               "paper_2006_15698_amd/csrc/kern_fp32.hip"],
+}
 
 
 def _code_only(text):
@@ -72,11 +75,11 @@ def _code_only(text):
     return " ".join(text.split())
 
 
-def kernel_source_hash():
-    """Hash of the stage kernels' code: counters taken on other code are
+def kernel_source_hash(precision="fp64"):
+    """Hash of the stage kernel's code: counters taken on other code are
     stale."""
     h = hashlib.sha256()
-    for f in STAGE_SOURCES:
+    for f in STAGE_SOURCES[precision]:
         with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
@@ -93,7 +96,7 @@ def measured_traffic(workload, precision, options):
     except (OSError, ValueError):
         return None
     ent = rec.get(f"{workload}:{precision}")
-    if not ent or ent.get("kernel_src") != kernel_source_hash() or ent.get("options") != options:
+    if not ent or ent.get("kernel_src") != kernel_source_hash(precision) or ent.get("options") != options:
         return None
     return ent.get("bytes_per_launch")
 
