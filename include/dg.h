@@ -115,8 +115,9 @@ int dg_set_precision(dg_ctx* ctx, int mode);
  * DG_OPT_XCD_REMAP: 1 gives each of the 8 XCDs of the MI355X (each with
  *   its own L2) a contiguous part of the visiting order; 0 leaves the
  *   hardware's round-robin spread of workgroups over the XCDs.
- * Defaults: the fastest measured setting for the mesh and p (see
- * dg_get_option). */
+ * Defaults (read back with dg_get_option): DG_EXCHANGE_NEIGHBOUR,
+ * DG_ORDER_PENCIL with 16 x 8 pencils and DG_OPT_XCD_REMAP 1, the fastest
+ * setting measured on the Taylor-Green workloads at p = 3, 4 and 6. */
 enum {
   DG_OPT_EXCHANGE = 1,
   DG_OPT_XCD_REMAP = 2,
@@ -131,8 +132,10 @@ int dg_set_option(dg_ctx* ctx, int key, int value);
 /* Current value of an option into *value. */
 int dg_get_option(const dg_ctx* ctx, int key, int* value);
 
-/* Bytes of device workspace that the compute calls need (face-trace
- * ping-pong buffers and reduction partials).  Depends on the mesh and p. */
+/* Bytes of device workspace that the compute calls need (the second state
+ * buffer of the neighbour-read exchange, the face-trace ping-pong buffers,
+ * reduction partials and the adjoint's two state-sized buffers).  Depends
+ * on the mesh and p. */
 size_t dg_workspace_bytes(const dg_ctx* ctx);
 
 /* Hand the context a caller-owned device workspace of at least
