@@ -289,8 +289,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}): this build "
-              "measures one GPU's share of the mesh; the multi-GPU face exchange is not built.",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}): it measures "
+              "one GPU's share of the mesh; the face exchange between GPUs is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

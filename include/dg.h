@@ -54,7 +54,7 @@ typedef struct dg_ctx dg_ctx;
 enum {
   DG_OK = 0,
   DG_EINVAL = -1,        /* bad argument (NULL, size, range) */
-  DG_EUNSUPPORTED = -2,  /* valid request outside what this build supports */
+  DG_EUNSUPPORTED = -2,  /* valid request outside what the library supports */
   DG_EHIP = -3,          /* HIP runtime error (launch, copy, sync) */
   DG_EALIAS = -4,        /* forbidden overlap between arrays */
   DG_ENONPHYSICAL = -5,  /* dg_check_state found rho<=0, p<=0 or NaN/Inf */
@@ -232,7 +232,7 @@ void dg_batch_destroy(dg_batch* b);
 int dg_batch_set_stream(dg_batch* b, void* hip_stream);
 /* FP64 (default) or FP32 matrix-core contractions for every mesh. */
 int dg_batch_set_precision(dg_batch* b, int mode);
-/* Elements per workgroup for degree p (values the build provides: see
+/* Elements per workgroup for degree p (values the library provides: see
  * dg_batch_tile_options); changes the work list, so call it before
  * dg_batch_set_workspace. */
 int dg_batch_set_tile(dg_batch* b, int p, int epb);

@@ -193,7 +193,7 @@ class DG:
 
     def dt_cfl(self, Q, cfl):
         """Time step dt = CFL / ((2p+1) max_rate(Q)).  The paper gives no CFL
-        rule; this one is the build's reading, used only to pick dt."""
+        rule; this one is a reading of ours, used only to pick dt."""
         return cfl / ((2 * self.p + 1) * self.max_rate(Q))
 
     def check_state(self, Q):

@@ -1,6 +1,6 @@
 """FP32 matrix-core form (contractions on FP32 deviations, FP64 anchors,
 LF, lift and RK) against the FP64 oracle and the FP64 GPU path.  The paper
-has no FP32 data, so these bars are the build's own statement of the FP32
+has no FP32 data, so these bars are our own statement of the FP32
 error (summand-scaled, as for FP64), not a parity claim."""
 
 import math
