@@ -2,6 +2,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -56,7 +57,13 @@ Layout layout(const dg_batch* b) {
 
 void build_items(dg_batch* b) {
   b->items.clear();
-  for (int i = 0; i < b->count; ++i) {
+  // meshes grouped by degree, highest first: blocks that run at the same
+  // time mostly execute the same (N, tile) variant, and the costliest items
+  // come first (a little faster with the FP32 form, results unchanged)
+  std::vector<int> order(b->count);
+  for (int i = 0; i < b->count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->inst[a].N > b->inst[c].N; });
+  for (int i : order) {
     DGBatchInst& I = b->inst[i];
     I.epb = b->epb_for_N[I.N];
     // blocks of up to epb consecutive elements of one x-row

@@ -371,7 +371,8 @@ class Batch:
 
     def __del__(self):
         b = getattr(self, "b", None)
-        if b:
+        # at interpreter exit the module's functions may already be gone
+        if b and dg_batch_destroy is not None:
             dg_batch_destroy(b)
             self.b = None
 
@@ -440,7 +441,8 @@ class Solver:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
+        # at interpreter exit the module's functions may already be gone
+        if ctx and dg_destroy is not None:
             dg_destroy(ctx)
             self.ctx = None
 
