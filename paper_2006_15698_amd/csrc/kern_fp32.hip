@@ -37,9 +37,8 @@ k_stage32(DGTables tb, double* __restrict__ Q, double* __restrict__ RR, const ch
   dgdev::stage_body32<N, MODE, EPB, NT>(tb, Q, RR, Tin, Tout, rka, rkb, dt, first, blockIdx.x * EPB, smem, threadIdx.x);
 }
 
-// At N=5 the body needs a few registers more than four waves per SIMD allow
-// (131 + 4); holding it to four (two spilled registers) is 6% faster there.
-// At N=4 the same bound spills four registers and is slower.
+// At N=5 the bound holds the body to four waves per SIMD (128 registers);
+// at N=4 it fits there by itself (122 VGPRs + 4 accumulation registers).
 template <int N, int MODE>
 __global__ void __launch_bounds__(FCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(N == 5 ? 4 : 1, 8)))
 k_stage_nb32(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,

@@ -52,9 +52,9 @@ k_stage(DGTables tb, double* __restrict__ Q, double* __restrict__ RR,
 }
 
 // Neighbour-read variant: Qin -> Qout (different buffers), no trace buffers;
-// element blocks visited in the order `ord`.  At N=4 the body needs 104
-// VGPRs (four waves per SIMD); holding it to 96 for a fifth wave spills a
-// few registers and is still about 4% faster.
+// element blocks visited in the order `ord`.  At N=4 the bound holds the
+// body to 96 VGPRs, so that five workgroups fit on a CU instead of four
+// (about 4% faster).
 template <int N, int MODE>
 __global__ void __launch_bounds__(Cfg<N>::NT) __attribute__((amdgpu_waves_per_eu(N == 4 ? 5 : 1, 8)))
 k_stage_nb(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,

@@ -164,11 +164,11 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     lpr[m] = tb.lp[m];
   }
 
-  // ---- A: every global load of the block is issued before any is waited
+  // ---- A: the state loads of the block are issued before any is waited
   //         for, in the order of use: own node, the x-neighbours' nodes,
-  //         the y/z neighbour traces (loads consumed by their FMA chains),
-  //         and last the residual, which stays in flight through the face
-  //         and volume phases (the load counter completes in order).
+  //         the y/z neighbour traces (loads consumed by their FMA chains;
+  //         the load counter completes in order).  The residual, needed
+  //         only in D, is loaded at the start of C.
   const bool nthr = tid < NODES;
   const int el = tid / N3;
   const int t = tid - el * N3;
@@ -212,16 +212,8 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
       nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;
     }
   }
-  // unconditional as well: the first stage reads the residual and ignores it
-  if (MODE != 0) {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + lofs];
-  } else {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = 0.0;
-  }
   // the 1-D tables, from uniform (scalar) kernarg reads: a per-thread
-  // vector read would be waited for behind the residual loads above
+  // vector read would be waited for behind the neighbour loads above
   if (tid < N * N) {
     double v = 0.0;
 #pragma unroll
@@ -286,6 +278,16 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   }
   __syncthreads();   // last reads of sQ; sF reuses it
 
+  // the residual, needed only in D: loaded here, its latency overlaps the
+  // volume phase, and its registers are not held through the face phase
+  // (unconditional: the first stage reads the residual and ignores it)
+  if (MODE != 0) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + lofs];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r[f] = 0.0;
+  }
   // ---- C: volume contraction + lift, one direction at a time
   const double rinv = 1.0 / q[0];
   const double pr = tb.gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * rinv);

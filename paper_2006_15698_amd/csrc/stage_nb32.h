@@ -2,8 +2,9 @@
 //
 // The block structure of stage_nb_body (stage_nb.h: EPB consecutive
 // elements of one x-row, the left and right x-neighbours staged in LDS,
-// y/z-neighbour lines read by waves that each handle one face, every load
-// issued before the first wait) with the arithmetic of the FP32 form
+// y/z-neighbour lines read by waves that each handle one face, the state
+// loads issued before the first wait, the residual loaded after the face
+// phase) with the arithmetic of the FP32 form
 // (stage_fp32.h):
 //   traces:  T = a + sum_m l_m(+-1) (Q_m - a), a = the FP64 state at the
 //            element's first node, the sum in FP32.  The FP32 deviations
@@ -135,7 +136,7 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
     lpr[m] = tb.lp32[m];
   }
 
-  // ---- A: every global load before the first wait (see stage_nb_body)
+  // ---- A: every state load before the first wait (see stage_nb_body)
   const bool nthr = tid < NODES;
   const int el = tid / N3;
   const int t = tid - el * N3;
@@ -173,13 +174,6 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
     } else {
       nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;
     }
-  }
-  if (MODE != 0) {   // unconditional; the first stage reads and ignores it
-#pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + lofs];
-  } else {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) r[f] = 0.0;
   }
   // tables from uniform (scalar) kernarg reads
   if (tid < N * N) {
@@ -264,6 +258,15 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
   }
   __syncthreads();   // last reads of sD; sF and sV reuse it
 
+  // the residual, needed only at the end: loaded here (unconditional; the
+  // first stage reads and ignores it)
+  if (MODE != 0) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + lofs];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r[f] = 0.0;
+  }
   // ---- C: per direction, matrix-core contraction of the flux deviations.
   // v_mfma_f32_16x16x4_f32: A[i][k] from lane (i = l%16, k = l/16),
   // B[k][j] from lane (k = l/16, j = l%16), D[i][j] in lane j = l%16,
