@@ -43,7 +43,7 @@ def _rel(a, b):
     return float(np.max(d / scale))
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("p", range(0, 8))
 def test_stage_by_stage(dgm, p):
     """Each of the five stages, called one at a time through dg_rk_stage."""
     import torch
@@ -207,12 +207,14 @@ def test_tgv_c2_full_run_drift(dgm):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("p", [1, 3, 4, 6])
+@pytest.mark.parametrize("p", range(0, 8))
 def test_exchange_schemes_bitwise_equal(dgm, p, prec):
     """Neighbour reads (with and without the XCD block mapping) and the
     face-trace buffers give bit-identical RHS, single stages (odd stage
     count: ping-pong copy back) and multi-step runs."""
     import torch
+    if prec == "fp32" and p == 0:
+        pytest.skip("the FP32 form starts at p = 1 (no contraction at p = 0)")
     n = (5, 3, 4)
     Q0 = _dev(W.random_smooth(n, p, seed=90 + p, noise=0.02))
     outs = []
