@@ -24,8 +24,8 @@ TUNED_PATH = os.path.join(HERE, "tuned_tiles.json")
 
 
 def _uniform_state(n, p, count):
-    """A smooth periodic state of every mesh (values only need to be
-    physical: the timing does not depend on them)."""
+    """A smooth periodic state of every mesh; every tile is timed on the
+    same state (the stage time depends a little on the data values)."""
     N = p + 1
     ar = torch.arange(n, dtype=torch.float64)
     x = (ar.view(1, 1, n, 1, 1, 1) + 0.5) / n
