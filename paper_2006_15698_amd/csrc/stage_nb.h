@@ -289,7 +289,7 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     for (int f = 0; f < 5; ++f) r[f] = 0.0;
   }
   // ---- C: volume contraction + lift, one direction at a time
-  const double rinv = 1.0 / q[0];
+  const double rinv = recip(q[0]);
   const double pr = tb.gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * rinv);
   double acc[5];
 #pragma unroll
