@@ -66,7 +66,7 @@ __device__ __forceinline__ int vneighbour(const DGTables& tb, int e, int d, int 
 // out += (dF^d/dQ)^T g at state q (Eq. (2) with the pressure of Eq. (3)).
 template <int d>
 __device__ __forceinline__ void flux_vjp(const double* q, const double* g, double gm1, double* out) {
-  const double r = 1.0 / q[0];
+  const double r = dgdev::recip(q[0]);
   const double u0 = q[1] * r, u1 = q[2] * r, u2 = q[3] * r;
   const double ud = d == 0 ? u0 : (d == 1 ? u1 : u2);
   const double pr = gm1 * (q[4] - 0.5 * (q[1] * u0 + q[2] * u1 + q[3] * u2));
@@ -85,14 +85,14 @@ __device__ __forceinline__ void flux_vjp(const double* q, const double* g, doubl
 // Local wave speed l = |u_d| + c and its gradient dl/dq.
 template <int d>
 __device__ __forceinline__ double wave_speed_grad(const double* q, double gamma, double gm1, double* dl) {
-  const double r = 1.0 / q[0];
+  const double r = dgdev::recip(q[0]);
   const double u0 = q[1] * r, u1 = q[2] * r, u2 = q[3] * r;
   const double ud = d == 0 ? u0 : (d == 1 ? u1 : u2);
   const double usq = u0 * u0 + u1 * u1 + u2 * u2;
   const double e = gm1 * (q[4] * r - 0.5 * usq);  // p / rho
-  const double c = sqrt(gamma * e);
+  const double c = dgdev::root(gamma * e);
   const double sg = ud >= 0.0 ? 1.0 : -1.0;
-  const double k = gamma / (2.0 * c);
+  const double k = gamma * dgdev::recip(2.0 * c);
   // de/drho = gm1 (-E/rho + |u|^2)/rho, de/dm_k = -gm1 u_k / rho, de/dE = gm1 / rho
   dl[0] = sg * (-ud * r) + k * gm1 * (-q[4] * r + usq) * r;
   dl[1] = (d == 0 ? sg * r : 0.0) - k * gm1 * u0 * r;
