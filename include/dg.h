@@ -260,14 +260,16 @@ int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps);
 
 /* Opt-in per-launch timing for benchmarks.  While on, the context brackets
  * every kernel it launches with HIP events on its stream (a few microseconds
- * of overhead per launch).  Kinds: 0 face-trace kernel, 1 RK stage kernel,
- * 2 RHS kernel, 3 adjoint kernels, 4 reductions.  Switching on clears the
- * record; at most 65536 launches are recorded. */
+ * of overhead per launch).  Kinds: 0 face-trace kernel, 1 RK stage kernel of
+ * stages 2..5, 2 RHS kernel, 3 adjoint kernels, 4 reductions, 5 RK stage
+ * kernel of the first stage (whose coefficient a is zero, so it writes the
+ * residual without reading it).  Switching on clears the record; at most
+ * 65536 launches are recorded. */
 int dg_set_timing(dg_ctx* ctx, int on);
 
 /* SYNCHRONISING.  Summed milliseconds ms[k] and launch counts count[k] for
- * the five kinds above since timing was switched on.  HOST arrays of 5. */
-int dg_timing_read(dg_ctx* ctx, double ms[5], int64_t count[5]);
+ * the six kinds above since timing was switched on.  HOST arrays of 6. */
+int dg_timing_read(dg_ctx* ctx, double ms[6], int64_t count[6]);
 
 #ifdef __cplusplus
 }

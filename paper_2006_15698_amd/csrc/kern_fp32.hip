@@ -58,6 +58,8 @@ int stage_nb32_n(const dg_ctx* c, const double* Qin, double* Qout, double* RR, i
   const dim3 blk(FCfg<N>::NT);
   if (mode == 0)
     hipLaunchKernelGGL((k_stage_nb32<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
+  else if (first)
+    hipLaunchKernelGGL((k_stage_nb32<N, 2>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
   else
     hipLaunchKernelGGL((k_stage_nb32<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
   return (int)hipGetLastError();

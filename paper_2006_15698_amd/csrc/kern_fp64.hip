@@ -180,6 +180,8 @@ int launch_stage_nb_n(const dg_ctx* c, const double* Qin, double* Qout, double* 
   const dim3 blk(Cfg<N>::NT);
   if (mode == 0)
     hipLaunchKernelGGL((k_stage_nb<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
+  else if (first)
+    hipLaunchKernelGGL((k_stage_nb<N, 2>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
   else
     hipLaunchKernelGGL((k_stage_nb<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, first, ord);
   return (int)hipGetLastError();

@@ -118,8 +118,11 @@ __device__ __forceinline__ void face_flux(const double* own, const double* nbq, 
 }
 
 // Elements [e0, e0 + ne) of one x-row, ne <= EPB.  MODE 0: RR = dQ/dt (Qout
-// unused).  MODE 1: RK stage, res in place, Qout = Qin + b res.  smem:
-// NbSmem<N,EPB>::size doubles.
+// unused).  MODE 1: RK stage, res in place (res = a res + dt dQ/dt, or
+// dt dQ/dt when `first` is set), Qout = Qin + b res.  MODE 2: the first RK
+// stage, whose coefficient a is zero: res = dt dQ/dt is written and the old
+// res is not read (40 of the 160 bytes per node).  smem: NbSmem<N,EPB>::size
+// doubles.
 template <int N, int MODE, int EPB, int NT>
 __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* __restrict__ Qin,
                                               double* __restrict__ Qout, double* __restrict__ RR, double rka,
@@ -280,8 +283,8 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
 
   // the residual, needed only in D: loaded here, its latency overlaps the
   // volume phase, and its registers are not held through the face phase
-  // (unconditional: the first stage reads the residual and ignores it)
-  if (MODE != 0) {
+  // (unconditional in MODE 1: with `first` set it is read and ignored)
+  if (MODE == 1) {
 #pragma unroll
     for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + lofs];
   } else {
@@ -332,7 +335,7 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   } else {
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      r[f] = first ? dt * acc[f] : fma(rka, r[f], dt * acc[f]);
+      r[f] = (MODE == 2 || first) ? dt * acc[f] : fma(rka, r[f], dt * acc[f]);
       q[f] = fma(rkb, r[f], q[f]);
     }
     if (act) {

@@ -84,7 +84,8 @@ __device__ __forceinline__ void face_flux32(const float* sD, const double* sAnc,
 }
 
 // Elements [e0, e0 + ne) of one x-row, ne <= EPB.  MODE 0: RR = dQ/dt.
-// MODE 1: RK stage (res = RR in place).  smem: Nb32Smem<N,EPB>::bytes.
+// MODE 1: RK stage (res = RR in place).  MODE 2: the first RK stage (a = 0:
+// res written, not read).  smem: Nb32Smem<N,EPB>::bytes.
 template <int N, int MODE, int EPB, int NT>
 __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double* __restrict__ Qin,
                                                 double* __restrict__ Qout, double* __restrict__ RR, double rka,
@@ -258,9 +259,9 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
   }
   __syncthreads();   // last reads of sD; sF and sV reuse it
 
-  // the residual, needed only at the end: loaded here (unconditional; the
-  // first stage reads and ignores it)
-  if (MODE != 0) {
+  // the residual, needed only at the end: loaded here (unconditional in
+  // MODE 1: with `first` set it is read and ignored)
+  if (MODE == 1) {
 #pragma unroll
     for (int f = 0; f < 5; ++f) r[f] = RR[f * EN3 + lofs];
   } else {
@@ -350,7 +351,7 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
   } else {
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      r[f] = first ? dt * acc5[f] : fma(rka, r[f], dt * acc5[f]);
+      r[f] = (MODE == 2 || first) ? dt * acc5[f] : fma(rka, r[f], dt * acc5[f]);
       q[f] = fma(rkb, r[f], q[f]);
     }
     if (act) {

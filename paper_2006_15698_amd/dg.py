@@ -263,7 +263,7 @@ def dg_check_state(ctx, Q):
     return True
 
 
-TIMING_KINDS = ("trace", "stage", "rhs", "vjp", "reduce")
+TIMING_KINDS = ("trace", "stage", "rhs", "vjp", "reduce", "stage_first")
 
 
 def dg_set_timing(ctx, on):
@@ -272,8 +272,8 @@ def dg_set_timing(ctx, on):
 
 def dg_timing_read(ctx):
     """{kind: (milliseconds, launches)} since timing was switched on."""
-    ms = (ctypes.c_double * 5)()
-    cnt = (ctypes.c_int64 * 5)()
+    ms = (ctypes.c_double * len(TIMING_KINDS))()
+    cnt = (ctypes.c_int64 * len(TIMING_KINDS))()
     _check(_lib.dg_timing_read(ctx, ms, cnt))
     return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_KINDS)}
 

@@ -324,3 +324,36 @@ def test_graph_steps_bitwise_equal_every_replay(dgm, prec):
         torch.cuda.synchronize()
         assert torch.equal(Qe, Qg) and torch.equal(re, rg), (k, ns)
         del junk
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("exchange", ["neighbour", "traces"])
+def test_first_stage_ignores_residual_and_timing_kinds(dgm, prec, exchange):
+    """The first stage (coefficient a = 0) gives the same state and residual
+    whatever the residual held before (NaN included), and the per-launch
+    timing files its launches under their own kind: K steps are K
+    first-stage launches and 4 K launches of stages 2..5."""
+    import torch
+    n, p, K = (5, 4, 6), 3, 3
+    print(f"[first stage {prec} {exchange}]", flush=True)
+    s = dgm.Solver(n, p, precision=dgm.DG_FP64 if prec == "fp64" else dgm.DG_FP32_MFMA)
+    s.set_option(dgm.DG_OPT_EXCHANGE, dgm.DG_EXCHANGE_NEIGHBOUR if exchange == "neighbour"
+                 else dgm.DG_EXCHANGE_TRACES)
+    Q0 = _dev(W.random_smooth(n, p, seed=150, noise=0.02))
+    dt = 0.3 * s.dt_cfl(Q0, 1.0)
+    outs = []
+    for fill in (0.0, float("nan"), 1e300):
+        Q, r = Q0.clone(), torch.full_like(Q0, fill)
+        s.rk_stage(0, Q, r, dt)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(Q).all()) and bool(torch.isfinite(r).all()), fill
+        outs.append((Q, r))
+    for Q, r in outs[1:]:
+        assert torch.equal(Q, outs[0][0]) and torch.equal(r, outs[0][1])
+    Q, r = Q0.clone(), torch.zeros_like(Q0)
+    dgm.dg_set_timing(s.ctx, True)
+    s.step(Q, r, dt, nsteps=K)
+    t = dgm.dg_timing_read(s.ctx)
+    dgm.dg_set_timing(s.ctx, False)
+    assert t["stage_first"][1] == K and t["stage"][1] == 4 * K
+    assert t["stage_first"][0] > 0 and t["stage"][0] > 0
