@@ -51,12 +51,12 @@ __device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, const dou
   // items are row-aligned blocks: the last block of a row may be short
   const int x0 = e0 % I.tab.nx;
   const int ne = dgdev::imin(I.epb, I.tab.nx - x0);
-#define DG_CASE(n, e)                                                                                  \
-  case n * 64 + e:                                                                                     \
-    if (F32)                                                                                           \
-      dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid); \
-    else                                                                                               \
-      dgdev::stage_nb_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid);   \
+#define DG_CASE(n, e)                                                                                        \
+  case n * 64 + e:                                                                                           \
+    if (F32)                                                                                                 \
+      dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid);       \
+    else                                                                                                     \
+      dgdev::stage_nb_body<n, MODE, e, BNT, true>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid); \
     break;
   switch (key) { DG_BATCH_VARIANTS(DG_CASE) default: break; }
 #undef DG_CASE

@@ -54,7 +54,9 @@ k_stage(DGTables tb, double* __restrict__ Q, double* __restrict__ RR,
 // Neighbour-read variant: Qin -> Qout (different buffers), no trace buffers;
 // element blocks visited in the order `ord`.  At N=4 the bound holds the
 // body to 96 VGPRs, so that five workgroups fit on a CU instead of four
-// (about 4% faster).
+// (about 4% faster).  The y/z neighbour lines are read by point pairs at
+// N=7 only, where that is 8% faster (at N=4, 5, 6 and 8 it was even or
+// 2-7% slower).
 template <int N, int MODE>
 __global__ void __launch_bounds__(Cfg<N>::NT) __attribute__((amdgpu_waves_per_eu(N == 4 ? 5 : 1, 8)))
 k_stage_nb(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,
@@ -63,7 +65,7 @@ k_stage_nb(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qou
   __shared__ double smem[dgdev::NbSmem<N, EPB>::size];
   int e0, ne;
   dgdev::block_elements<EPB>(tb, ord, blockIdx.x, gridDim.x, e0, ne);
-  dgdev::stage_nb_body<N, MODE, EPB, NT>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, smem, threadIdx.x);
+  dgdev::stage_nb_body<N, MODE, EPB, NT, (N == 7)>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, smem, threadIdx.x);
 }
 
 // ---- reductions -----------------------------------------------------------

@@ -99,6 +99,94 @@ __device__ __forceinline__ void chunk_trace(const double* __restrict__ base, int
   }
 }
 
+// Paired neighbour lines.  On a y- or z-face, the line nodes of two face
+// points next to each other along x (tangential index a, a + 1 of one row b)
+// are next to each other in memory for every m, so one 16-byte load brings
+// both: a lane takes such a pair of points, and the pairs of both faces of a
+// direction (the - and + neighbour) share one wave, which halves the load
+// instructions of the neighbour lines against one point per lane.  Rows of
+// odd length end in a pair that overlaps the previous one (a = N-2, N-1).
+// Used where the pairs of both faces fit one wave.
+template <int N, int EPB, int NW>
+struct PairLines {
+  static constexpr int P = (N + 1) / 2;          // pairs per row of a face
+  static constexpr int LPF = EPB * N * P;        // lanes per face
+  static constexpr bool on = N >= 2 && NW >= 2 && 2 * LPF <= 64;
+  static constexpr int FS = NW >= 4 ? 2 : 1;     // field groups: waves per direction
+  static constexpr int WAVES = 2 * FS;           // waves that load neighbour lines
+};
+
+// Traces of fields [F0, F1) on the faces of direction D (SIDE from the lane)
+// for the lane's pair of points, written to the face-flux region sH at
+// (face * 5 + f) * FP + fel * N^2 + pt, face = 2 + 2 (D - 1) + side.  The
+// FMA chain of each point is that of chunk_trace, so the traces are bitwise
+// the same.  Points of absent elements get a valid placeholder state.
+template <int N, int EPB, int D, int F0, int F1>
+__device__ __forceinline__ void pair_trace(const double* __restrict__ Qin, int64_t EN3, int em, int ep, int ne,
+                                           int lane, const double* lmr, const double* lpr, double* sH) {
+  constexpr int N2 = N * N, N3 = N2 * N, FP = EPB * N2;
+  constexpr int P = (N + 1) / 2, LPF = EPB * N * P;
+  if (lane >= 2 * LPF) return;
+  const int side = lane >= LPF;
+  const int j = lane - side * LPF;
+  const int fel = j / (N * P);
+  const int rj = j - fel * (N * P);
+  const int b = rj / P, q = rj - b * P;
+  const int a0 = 2 * q < N - 2 ? 2 * q : N - 2;
+  const bool dup = 2 * q > N - 2;                // overlapping last pair: a0 is covered already
+  const int pt = a0 + N * b;
+  double* h = sH + (2 + 2 * (D - 1) + side) * 5 * FP + fel * N2 + pt;
+  if (fel < ne) {
+    const double* qb = Qin + (int64_t)(side ? ep : em) * N3 + fel * N3 + tnode<N>(D, 0, pt);
+    double c[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) c[m] = side ? lmr[m] : lpr[m];
+    // Up to N = 5: fields in groups of at most 16 loads, each group's loads
+    // issued before the first of them is used, held there by a scheduling
+    // barrier (left to itself the compiler waits for each load before issuing
+    // the next, which costs 10-20% at these degrees).  From N = 6 the
+    // compiler's own order is kept: there the registers it saves let one
+    // more workgroup onto a CU.
+    constexpr bool GROUPED = N <= 5;
+    constexpr int G = GROUPED ? 16 / N : 1;
+#pragma unroll
+    for (int g0 = F0; g0 < F1; g0 += G) {
+      constexpr int GM = G;
+      double2 w[GM][N];
+#pragma unroll
+      for (int k = 0; k < GM; ++k) {
+        if (g0 + k < F1) {
+          const double* qn = qb + (g0 + k) * EN3;
+#pragma unroll
+          for (int m = 0; m < N; ++m)
+            __builtin_memcpy(&w[k][m], qn + (tnode<N>(D, m, pt) - tnode<N>(D, 0, pt)), 16);
+        }
+      }
+      if constexpr (GROUPED) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < GM; ++k) {
+        if (g0 + k < F1) {
+          double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            v0 = fma(c[m], w[k][m].x, v0);
+            v1 = fma(c[m], w[k][m].y, v1);
+          }
+          if (!dup) h[(g0 + k) * FP] = v0;
+          h[(g0 + k) * FP + 1] = v1;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int f = F0; f < F1; ++f) {
+      const double v = f == 0 ? 1.0 : (f == 4 ? 2.5 : 0.0);
+      h[f * FP] = v;
+      h[f * FP + 1] = v;
+    }
+  }
+}
+
 // Lax-Friedrichs flux at point pt of face (D, SIDE) of the element whose
 // state is at `own` (LDS, field stride NH); the neighbour's trace comes
 // from LDS (`nbq`, x-faces) or from registers (`nbv`, y- and z-faces).
@@ -122,8 +210,9 @@ __device__ __forceinline__ void face_flux(const double* own, const double* nbq, 
 // dt dQ/dt when `first` is set), Qout = Qin + b res.  MODE 2: the first RK
 // stage, whose coefficient a is zero: res = dt dQ/dt is written and the old
 // res is not read (40 of the 160 bytes per node).  smem: NbSmem<N,EPB>::size
-// doubles.
-template <int N, int MODE, int EPB, int NT>
+// doubles.  PAIRS: read the y/z neighbour lines by point pairs (PairLines)
+// where the configuration allows it.
+template <int N, int MODE, int EPB, int NT, bool PAIRS>
 __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* __restrict__ Qin,
                                               double* __restrict__ Qout, double* __restrict__ RR, double rka,
                                               double rkb, double dt, int first, int e0, int ne, double* smem,
@@ -198,21 +287,37 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     }
   }
   const int wave = tid >> 6, lane = tid & 63;
-  double nb[RNDG][5];
+  constexpr bool PON = PAIRS && PairLines<N, EPB, NW>::on;
+  using PL = PairLines<N, EPB, NW>;
+  double nb[PON ? 1 : RNDG][5];
+  if constexpr (PON) {
+    // y/z neighbour traces by point pairs, straight into the face-flux
+    // region; phase B reads each back in the thread that then overwrites it
+    // with the flux, so the region serves both without another barrier
+    constexpr int F1 = PL::FS == 2 ? 3 : 5;
+    switch (wave) {   // uniform over the wave
+      case 0: pair_trace<N, EPB, 1, 0, F1>(Qin, EN3, eym, eyp, ne, lane, lmr, lpr, sH); break;
+      case 1: pair_trace<N, EPB, 2, 0, F1>(Qin, EN3, ezm, ezp, ne, lane, lmr, lpr, sH); break;
+      case 2: if (PL::FS == 2) pair_trace<N, EPB, 1, 3, 5>(Qin, EN3, eym, eyp, ne, lane, lmr, lpr, sH); break;
+      case 3: if (PL::FS == 2) pair_trace<N, EPB, 2, 3, 5>(Qin, EN3, ezm, ezp, ne, lane, lmr, lpr, sH); break;
+      default: break;
+    }
+  } else {
 #pragma unroll
-  for (int u = 0; u < RNDG; ++u) {
-    const int s = wave + u * NW;
-    const int i = (s < S::NYZ ? S::chunk(s) : 0) * 64 + lane;
-    const int fel = i / N2, pt = i - fel * N2;
-    if (s < S::NYZ && i < FP && fel < ne) {
-      switch (S::face(s)) {   // uniform over the wave
-        case 2: chunk_trace<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-        case 3: chunk_trace<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-        case 4: chunk_trace<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-        default: chunk_trace<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+    for (int u = 0; u < RNDG; ++u) {
+      const int s = wave + u * NW;
+      const int i = (s < S::NYZ ? S::chunk(s) : 0) * 64 + lane;
+      const int fel = i / N2, pt = i - fel * N2;
+      if (s < S::NYZ && i < FP && fel < ne) {
+        switch (S::face(s)) {   // uniform over the wave
+          case 2: chunk_trace<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          case 3: chunk_trace<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          case 4: chunk_trace<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          default: chunk_trace<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+        }
+      } else {
+        nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;
       }
-    } else {
-      nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;
     }
   }
   // the 1-D tables, from uniform (scalar) kernarg reads: a per-thread
@@ -264,7 +369,16 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
       const int face = S::face(s);
       const int fel = i / N2, pt = i - fel * N2;
       const double* own = sQ + (fel + 1) * N3;
-      const double* nbv = nb[u < RNDG ? u : 0];
+      double nbl[5];
+      const double* nbv = nbl;
+      if constexpr (PON) {
+        if (face >= 2) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) nbl[f] = sH[(face * 5 + f) * FP + i];
+        }
+      } else {
+        nbv = nb[u < RNDG ? u : 0];
+      }
       const double g = tb.gamma, g1 = tb.gm1;
       double fs[5];
       switch (face) {   // uniform over the wave
