@@ -23,7 +23,7 @@ namespace dgdev {
 // Node index inside an element of the point with index m along direction d
 // and tangential index pt = a + N b (lower tangential axis fastest).
 template <int N>
-__device__ __forceinline__ int tnode(int d, int m, int pt) {
+__host__ __device__ __forceinline__ int tnode(int d, int m, int pt) {
   if (d == 0) return pt * N + m;                          // i = m, j = a, k = b
   if (d == 1) return (pt / N) * N * N + m * N + (pt % N); // j = m, i = a, k = b
   return m * N * N + pt;                                   // k = m, i = a, j = b

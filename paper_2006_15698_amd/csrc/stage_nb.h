@@ -116,6 +116,27 @@ struct PairLines {
   static constexpr int WAVES = 2 * FS;           // waves that load neighbour lines
 };
 
+// Lane -> pair of face points under PairLines: the face (side 0: the -
+// neighbour, 1: the + neighbour), the chunk element fel, the first point pt
+// of the pair (the pair is pt, pt + 1 of one row), and whether pt is already
+// covered by the row's previous pair.  Lanes from 2 LPF on hold no pair.
+template <int N, int EPB>
+struct PairLane {
+  int side, fel, pt;
+  bool dup;
+  __host__ __device__ explicit PairLane(int lane) {
+    constexpr int P = (N + 1) / 2, LPF = EPB * N * P;
+    side = lane >= LPF;
+    const int j = lane - side * LPF;
+    fel = j / (N * P);
+    const int rj = j - fel * (N * P);
+    const int b = rj / P, q = rj - b * P;
+    const int a0 = 2 * q < N - 2 ? 2 * q : N - 2;
+    dup = 2 * q > N - 2;
+    pt = a0 + N * b;
+  }
+};
+
 // Traces of fields [F0, F1) on the faces of direction D (SIDE from the lane)
 // for the lane's pair of points, written to the face-flux region sH at
 // (face * 5 + f) * FP + fel * N^2 + pt, face = 2 + 2 (D - 1) + side.  The
@@ -127,14 +148,9 @@ __device__ __forceinline__ void pair_trace(const double* __restrict__ Qin, int64
   constexpr int N2 = N * N, N3 = N2 * N, FP = EPB * N2;
   constexpr int P = (N + 1) / 2, LPF = EPB * N * P;
   if (lane >= 2 * LPF) return;
-  const int side = lane >= LPF;
-  const int j = lane - side * LPF;
-  const int fel = j / (N * P);
-  const int rj = j - fel * (N * P);
-  const int b = rj / P, q = rj - b * P;
-  const int a0 = 2 * q < N - 2 ? 2 * q : N - 2;
-  const bool dup = 2 * q > N - 2;                // overlapping last pair: a0 is covered already
-  const int pt = a0 + N * b;
+  const PairLane<N, EPB> pl(lane);
+  const int side = pl.side, fel = pl.fel, pt = pl.pt;
+  const bool dup = pl.dup;
   double* h = sH + (2 + 2 * (D - 1) + side) * 5 * FP + fel * N2 + pt;
   if (fel < ne) {
     const double* qb = Qin + (int64_t)(side ? ep : em) * N3 + fel * N3 + tnode<N>(D, 0, pt);

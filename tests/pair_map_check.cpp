@@ -1,0 +1,65 @@
+// Host check of the paired neighbour-line lane map (dgdev::PairLane and
+// dgdev::PairLines, compiled from the kernel's header): for every degree
+// and block size of the single-mesh and batched stage kernels, and both
+// face directions that use it, the lanes of a wave cover every point of
+// both faces of the block exactly once, each pair lies in one row, and the
+// two points' line nodes are neighbours in memory inside the element for
+// every m (so one 16-byte load fetches both).  Exit status 0 and "ok" on
+// success.
+#include <cstdio>
+#include <vector>
+
+#include "stage_nb.h"
+
+template <int N, int EPB, int NT>
+static int check() {
+  using PL = dgdev::PairLines<N, EPB, NT / 64>;
+  if (!PL::on) return 0;
+  constexpr int N2 = N * N, N3 = N2 * N, FP = EPB * N2;
+  if (2 * PL::LPF > 64) {
+    printf("N=%d EPB=%d: pairs of two faces do not fit a wave\n", N, EPB);
+    return 1;
+  }
+  for (int d = 1; d <= 2; ++d) {
+    std::vector<int> hits(2 * FP, 0);
+    for (int lane = 0; lane < 2 * PL::LPF; ++lane) {
+      const dgdev::PairLane<N, EPB> p(lane);
+      if (p.side < 0 || p.side > 1 || p.fel < 0 || p.fel >= EPB || p.pt < 0 || p.pt + 1 >= N2 ||
+          p.pt % N + 1 >= N) {
+        printf("N=%d EPB=%d lane %d: pair out of range\n", N, EPB, lane);
+        return 1;
+      }
+      for (int m = 0; m < N; ++m) {
+        const int n0 = d == 1 ? dgdev::tnode<N>(1, m, p.pt) : dgdev::tnode<N>(2, m, p.pt);
+        const int n1 = d == 1 ? dgdev::tnode<N>(1, m, p.pt + 1) : dgdev::tnode<N>(2, m, p.pt + 1);
+        if (n1 != n0 + 1 || n0 < 0 || n1 >= N3) {
+          printf("N=%d EPB=%d d=%d lane %d m %d: line nodes %d, %d not adjacent\n", N, EPB, d, lane, m, n0, n1);
+          return 1;
+        }
+      }
+      const int base = p.side * FP + p.fel * N2 + p.pt;
+      if (!p.dup) hits[base] += 1;
+      hits[base + 1] += 1;
+    }
+    for (int i = 0; i < 2 * FP; ++i) {
+      if (hits[i] != 1) {
+        printf("N=%d EPB=%d d=%d: face point %d written %d times\n", N, EPB, d, i, hits[i]);
+        return 1;
+      }
+    }
+  }
+  return 0;
+}
+
+int main() {
+  int bad = 0;
+  // single-mesh kernels (degree, elements per block, threads)
+  bad |= check<2, 16, 128>() | check<3, 9, 256>() | check<4, 4, 256>() | check<5, 2, 256>();
+  bad |= check<6, 1, 256>() | check<7, 1, 384>() | check<8, 1, 512>();
+  // batched kernel variants (256 threads)
+  bad |= check<2, 8, 256>() | check<2, 16, 256>() | check<3, 4, 256>() | check<3, 9, 256>();
+  bad |= check<4, 2, 256>() | check<4, 4, 256>() | check<5, 1, 256>() | check<5, 2, 256>() | check<6, 1, 256>();
+  if (bad) return 1;
+  printf("ok\n");
+  return 0;
+}

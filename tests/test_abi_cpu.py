@@ -155,3 +155,23 @@ def test_visiting_order_is_a_bijection(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "ok" in out.stdout
+
+
+def test_paired_line_lane_map(tmp_path):
+    """The paired neighbour-line lane map, compiled for the host from the
+    kernel's own header: both faces of a direction are covered point by
+    point exactly once, and each 16-byte load fetches the line nodes of two
+    points that are neighbours in memory inside the element."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "pair_map_check")
+    src = os.path.join(ROOT, "tests", "pair_map_check.cpp")
+    cmd = [hipcc, "-O1", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_2006_15698_amd", "csrc"), src, "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "ok" in out.stdout
