@@ -102,18 +102,19 @@ __device__ __forceinline__ void chunk_trace(const double* __restrict__ base, int
 // Paired neighbour lines.  On a y- or z-face, the line nodes of two face
 // points next to each other along x (tangential index a, a + 1 of one row b)
 // are next to each other in memory for every m, so one 16-byte load brings
-// both: a lane takes such a pair of points, and the pairs of both faces of a
-// direction (the - and + neighbour) share one wave, which halves the load
-// instructions of the neighbour lines against one point per lane.  Rows of
-// odd length end in a pair that overlaps the previous one (a = N-2, N-1).
-// Used where the pairs of both faces fit one wave.
+// both (a multi-dword access needs only dword alignment, so a pair may
+// start at an odd node).  A lane takes such a pair of points, and the pairs
+// of both faces of a direction (the - and + neighbour) share one wave,
+// which halves the load instructions of the neighbour lines against one
+// point per lane.  Rows of odd length end in a pair that overlaps the
+// previous one (a = N-2, N-1).  Used where the pairs of both faces fit one
+// wave.
 template <int N, int EPB, int NW>
 struct PairLines {
   static constexpr int P = (N + 1) / 2;          // pairs per row of a face
   static constexpr int LPF = EPB * N * P;        // lanes per face
   static constexpr bool on = N >= 2 && NW >= 2 && 2 * LPF <= 64;
   static constexpr int FS = NW >= 4 ? 2 : 1;     // field groups: waves per direction
-  static constexpr int WAVES = 2 * FS;           // waves that load neighbour lines
 };
 
 // Lane -> pair of face points under PairLines: the face (side 0: the -
@@ -167,10 +168,9 @@ __device__ __forceinline__ void pair_trace(const double* __restrict__ Qin, int64
     constexpr int G = GROUPED ? 16 / N : 1;
 #pragma unroll
     for (int g0 = F0; g0 < F1; g0 += G) {
-      constexpr int GM = G;
-      double2 w[GM][N];
+      double2 w[G][N];
 #pragma unroll
-      for (int k = 0; k < GM; ++k) {
+      for (int k = 0; k < G; ++k) {
         if (g0 + k < F1) {
           const double* qn = qb + (g0 + k) * EN3;
 #pragma unroll
@@ -180,7 +180,7 @@ __device__ __forceinline__ void pair_trace(const double* __restrict__ Qin, int64
       }
       if constexpr (GROUPED) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int k = 0; k < GM; ++k) {
+      for (int k = 0; k < G; ++k) {
         if (g0 + k < F1) {
           double v0 = 0.0, v1 = 0.0;
 #pragma unroll
