@@ -39,6 +39,11 @@ constexpr int arrmax(const int* a, int n) { return n == 0 ? 0 : cmax(a[0], arrma
 constexpr int kSmem64 = arrmax(kSizes64, sizeof(kSizes64) / sizeof(int));          // doubles
 constexpr int kSmem32 = (arrmax(kSizes32, sizeof(kSizes32) / sizeof(int)) + 7) / 8;  // doubles
 
+// How the FP64 variants read their y/z neighbour lines: partner-lane pairs
+// at even N, LDS-handed pairs at odd N.
+template <int N>
+constexpr int kLines64 = N % 2 == 0 ? dgdev::LINES_DPP : dgdev::LINES_LDS;
+
 template <int MODE, bool F32>
 __device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, const double* Qin, double* Qout, double* RR,
                                          double a, double b, int first, double* smem, int tid) {
@@ -56,7 +61,7 @@ __device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, const dou
     if (F32)                                                                                                 \
       dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid);       \
     else                                                                                                     \
-      dgdev::stage_nb_body<n, MODE, e, BNT, true>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid); \
+      dgdev::stage_nb_body<n, MODE, e, BNT, kLines64<n>>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid); \
     break;
   switch (key) { DG_BATCH_VARIANTS(DG_CASE) default: break; }
 #undef DG_CASE

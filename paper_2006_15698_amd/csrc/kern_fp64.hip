@@ -51,12 +51,20 @@ k_stage(DGTables tb, double* __restrict__ Q, double* __restrict__ RR,
   dgdev::stage_body<N, MODE, EPB, NT>(tb, Q, RR, Tin, Tout, rka, rkb, dt, first, blockIdx.x * EPB, smem, threadIdx.x);
 }
 
+// How the single-mesh stage reads its y/z neighbour lines: partner-lane
+// pairs at N = 2, 4, 6 (against one point per lane: N=6 10% faster, N=4
+// 6% beyond the MALL and even at 32^3, N=2 1-2%); LDS-handed pairs at
+// N = 7, where they are 8% faster (at N = 4, 5, 6 and 8 they were even or
+// 2-7% slower); one point per lane at N = 3, 5 and 8 (partner-lane pairs
+// take N = 8 past 128 registers).
+template <int N>
+constexpr int kLines = N == 7 ? dgdev::LINES_LDS
+                               : (N % 2 == 0 && N <= 6) ? dgdev::LINES_DPP : dgdev::LINES_POINT;
+
 // Neighbour-read variant: Qin -> Qout (different buffers), no trace buffers;
 // element blocks visited in the order `ord`.  At N=4 the bound holds the
 // body to 96 VGPRs, so that five workgroups fit on a CU instead of four
-// (about 4% faster).  The y/z neighbour lines are read by point pairs at
-// N=7 only, where that is 8% faster (at N=4, 5, 6 and 8 it was even or
-// 2-7% slower).
+// (about 4% faster).
 template <int N, int MODE>
 __global__ void __launch_bounds__(Cfg<N>::NT) __attribute__((amdgpu_waves_per_eu(N == 4 ? 5 : 1, 8)))
 k_stage_nb(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR,
@@ -65,7 +73,7 @@ k_stage_nb(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qou
   __shared__ double smem[dgdev::NbSmem<N, EPB>::size];
   int e0, ne;
   dgdev::block_elements<EPB>(tb, ord, blockIdx.x, gridDim.x, e0, ne);
-  dgdev::stage_nb_body<N, MODE, EPB, NT, (N == 7)>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, smem, threadIdx.x);
+  dgdev::stage_nb_body<N, MODE, EPB, NT, kLines<N>>(tb, Qin, Qout, RR, rka, rkb, dt, first, e0, ne, smem, threadIdx.x);
 }
 
 // ---- reductions -----------------------------------------------------------

@@ -26,6 +26,9 @@ namespace dgdev {
 
 __host__ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
+// How a stage reads its y/z neighbour lines (see stage_nb_body).
+enum { LINES_POINT = 0, LINES_LDS = 1, LINES_DPP = 2 };
+
 // Workgroup -> position in the visiting order that gives each XCD a
 // contiguous range: workgroups are dispatched round robin over the 8 XCDs,
 // so workgroup w runs on XCD w % 8 and is the (w / 8)-th of that XCD.  A
@@ -95,6 +98,54 @@ __device__ __forceinline__ void chunk_trace(const double* __restrict__ base, int
     double v = 0.0;
 #pragma unroll
     for (int m = 0; m < N; ++m) v = fma(SIDE ? lmr[m] : lpr[m], qn[tnode<N>(D, m, pt)], v);
+    out[f] = v;
+  }
+}
+
+// The partner lane's value (lanes 2k and 2k + 1 swap), by DPP.
+__device__ __forceinline__ double swap_adjacent(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// chunk_trace for even N, one point per lane: lanes 2k and 2k + 1 hold the
+// x-adjacent points pe = pt - s and pe + 1 (s = pt & 1) of one row, whose
+// line nodes form a 16-byte-aligned pair at every m (N even).  Each lane
+// loads the pair at m = 2j + s and takes its value at the other m of the
+// two from its partner, so a lane issues N/2 loads per field instead of N.
+// Same FMA chain as chunk_trace, so the traces are bitwise the same.  Both
+// lanes of a pair must be active.
+template <int N, int D, int SIDE>
+__device__ __forceinline__ void chunk_trace_x2(const double* __restrict__ base, int64_t EN3, int fel, int pt,
+                                               const double* lmr, const double* lpr, double* out) {
+  static_assert(N % 2 == 0, "pairs of x-adjacent points need an even N");
+  constexpr int N3 = N * N * N;
+  const int s = pt & 1;
+  const int pe = pt - s;
+  double2 w[5][N / 2];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double* qn = base + f * EN3 + fel * N3 + tnode<N>(D, 0, pe);
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const int off0 = tnode<N>(D, 2 * j, pe) - tnode<N>(D, 0, pe);
+      const int off1 = tnode<N>(D, 2 * j + 1, pe) - tnode<N>(D, 0, pe);
+      __builtin_memcpy(&w[f][j], qn + (s ? off1 : off0), 16);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const double px = swap_adjacent(w[f][j].x), py = swap_adjacent(w[f][j].y);
+      const double a = s ? py : w[f][j].x;   // this point at m = 2j
+      const double b = s ? w[f][j].y : px;   // this point at m = 2j + 1
+      v = fma(SIDE ? lmr[2 * j] : lpr[2 * j], a, v);
+      v = fma(SIDE ? lmr[2 * j + 1] : lpr[2 * j + 1], b, v);
+    }
     out[f] = v;
   }
 }
@@ -226,9 +277,12 @@ __device__ __forceinline__ void face_flux(const double* own, const double* nbq, 
 // dt dQ/dt when `first` is set), Qout = Qin + b res.  MODE 2: the first RK
 // stage, whose coefficient a is zero: res = dt dQ/dt is written and the old
 // res is not read (40 of the 160 bytes per node).  smem: NbSmem<N,EPB>::size
-// doubles.  PAIRS: read the y/z neighbour lines by point pairs (PairLines)
-// where the configuration allows it.
-template <int N, int MODE, int EPB, int NT, bool PAIRS>
+// doubles.  LINES: how the y/z neighbour lines are read: LINES_POINT one
+// point per lane (chunk_trace), LINES_LDS point pairs of both faces of a
+// direction per wave with the traces handed over in LDS (PairLines; where
+// the configuration allows it, else one point per lane), LINES_DPP point
+// pairs of partner lanes (chunk_trace_x2; even N).
+template <int N, int MODE, int EPB, int NT, int LINES>
 __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* __restrict__ Qin,
                                               double* __restrict__ Qout, double* __restrict__ RR, double rka,
                                               double rkb, double dt, int first, int e0, int ne, double* smem,
@@ -303,7 +357,8 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
     }
   }
   const int wave = tid >> 6, lane = tid & 63;
-  constexpr bool PON = PAIRS && PairLines<N, EPB, NW>::on;
+  constexpr bool PON = LINES == LINES_LDS && PairLines<N, EPB, NW>::on;
+  static_assert(LINES != LINES_DPP || N % 2 == 0, "partner-lane pairs need an even N");
   using PL = PairLines<N, EPB, NW>;
   double nb[PON ? 1 : RNDG][5];
   if constexpr (PON) {
@@ -325,11 +380,22 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
       const int i = (s < S::NYZ ? S::chunk(s) : 0) * 64 + lane;
       const int fel = i / N2, pt = i - fel * N2;
       if (s < S::NYZ && i < FP && fel < ne) {
-        switch (S::face(s)) {   // uniform over the wave
-          case 2: chunk_trace<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-          case 3: chunk_trace<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-          case 4: chunk_trace<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-          default: chunk_trace<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+        if constexpr (LINES == LINES_DPP) {
+          // (pairs of lanes share fel, and FP is even: both lanes of a pair
+          // take this branch or neither)
+          switch (S::face(s)) {   // uniform over the wave
+            case 2: chunk_trace_x2<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+            case 3: chunk_trace_x2<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+            case 4: chunk_trace_x2<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+            default: chunk_trace_x2<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          }
+        } else {
+          switch (S::face(s)) {   // uniform over the wave
+            case 2: chunk_trace<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+            case 3: chunk_trace<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+            case 4: chunk_trace<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+            default: chunk_trace<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          }
         }
       } else {
         nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;

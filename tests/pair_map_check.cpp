@@ -1,5 +1,6 @@
-// Host check of the paired neighbour-line lane map (dgdev::PairLane and
-// dgdev::PairLines, compiled from the kernel's header): for every degree
+// Host check of the paired neighbour-line lane maps (dgdev::PairLane and
+// dgdev::PairLines, and the partner-lane pairs of chunk_trace_x2, compiled
+// from the kernel's header).  LDS-handed pairs: for every degree
 // and block size of the single-mesh and batched stage kernels, and both
 // face directions that use it, the lanes of a wave cover every point of
 // both faces of the block exactly once, each pair lies in one row, and the
@@ -51,8 +52,36 @@ static int check() {
   return 0;
 }
 
+// Partner-lane pairs (chunk_trace_x2, even N): the even point pe of every
+// pair and pe + 1 lie in one row, and their line nodes are neighbours in
+// memory at an even offset inside the element for every m (so the pair is
+// 16-byte aligned whenever the element is, N^3 being even).
+template <int N>
+static int check_x2() {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  static_assert(N3 % 2 == 0, "even element size");
+  for (int d = 1; d <= 2; ++d) {
+    for (int pe = 0; pe < N2; pe += 2) {
+      if (pe % N + 1 >= N) {
+        printf("N=%d: pair at %d leaves its row\n", N, pe);
+        return 1;
+      }
+      for (int m = 0; m < N; ++m) {
+        const int n0 = d == 1 ? dgdev::tnode<N>(1, m, pe) : dgdev::tnode<N>(2, m, pe);
+        const int n1 = d == 1 ? dgdev::tnode<N>(1, m, pe + 1) : dgdev::tnode<N>(2, m, pe + 1);
+        if (n1 != n0 + 1 || n0 % 2 != 0 || n1 >= N3) {
+          printf("N=%d d=%d m=%d: pair at %d not an aligned pair of nodes (%d, %d)\n", N, d, m, pe, n0, n1);
+          return 1;
+        }
+      }
+    }
+  }
+  return 0;
+}
+
 int main() {
   int bad = 0;
+  bad |= check_x2<2>() | check_x2<4>() | check_x2<6>() | check_x2<8>();
   // single-mesh kernels (degree, elements per block, threads)
   bad |= check<2, 16, 128>() | check<3, 9, 256>() | check<4, 4, 256>() | check<5, 2, 256>();
   bad |= check<6, 1, 256>() | check<7, 1, 384>() | check<8, 1, 512>();
