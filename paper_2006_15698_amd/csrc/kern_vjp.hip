@@ -348,6 +348,45 @@ __device__ __forceinline__ void chunk_trace2(const double* __restrict__ Q, const
   }
 }
 
+// chunk_trace2 for even N by partner-lane pairs (as chunk_trace_x2 in
+// stage_nb.h): lanes 2k and 2k + 1 hold x-adjacent points whose line nodes
+// form a 16-byte pair at every m; each lane loads the Q and gR pairs at
+// m = 2j + (pt & 1) and takes the other m from its partner by DPP.  Same
+// FMA chains as chunk_trace2.  Both lanes of a pair must be active.
+template <int N, int D>
+__device__ __forceinline__ void chunk_trace2_x2(const double* __restrict__ Q, const double* __restrict__ G,
+                                                int64_t EN3, int64_t cofs, int pt, const double* cq,
+                                                const double* cg, double* qn, double* gn) {
+  static_assert(N % 2 == 0, "pairs of x-adjacent points need an even N");
+  const int s = pt & 1;
+  const int pe = pt - s;
+  double2 wq[5][N / 2], wg[5][N / 2];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const int64_t o = f * EN3 + cofs + (s ? vnode<N>(D, 2 * j + 1, pe) : vnode<N>(D, 2 * j, pe));
+      __builtin_memcpy(&wq[f][j], Q + o, 16);
+      __builtin_memcpy(&wg[f][j], G + o, 16);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double vq = 0.0, vg = 0.0;
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const double pqx = dgdev::swap_adjacent(wq[f][j].x), pqy = dgdev::swap_adjacent(wq[f][j].y);
+      const double pgx = dgdev::swap_adjacent(wg[f][j].x), pgy = dgdev::swap_adjacent(wg[f][j].y);
+      vq = fma(cq[2 * j], s ? pqy : wq[f][j].x, vq);
+      vg = fma(cg[2 * j], s ? pgy : wg[f][j].x, vg);
+      vq = fma(cq[2 * j + 1], s ? wq[f][j].y : pqx, vq);
+      vg = fma(cg[2 * j + 1], s ? wg[f][j].y : pgx, vg);
+    }
+    qn[f] = vq;
+    gn[f] = vg;
+  }
+}
+
 // Adjoint of this element's side of face (D, SIDE) at point pt: own traces
 // from LDS (sQ, sG slot `so`), the neighbour's from LDS (slot `sn`, x-faces)
 // or from registers.
@@ -456,11 +495,21 @@ k_vjp_nb(DGTables tb, const double* __restrict__ Q, const double* __restrict__ g
     const int i = (s < S::NYZ ? S::chunk(s) : 0) * 64 + lane;
     const int fel = i / N2, pt = i - fel * N2;
     if (s < S::NYZ && i < FP && fel < ne) {
-      switch (S::face(s)) {   // uniform over the wave; neighbour's face on the other side
-        case 2: chunk_trace2<N, 1>(Q, gR, EN3, (int64_t)(eym + fel) * N3, pt, lpr, lfp, qnb[u], gnb[u]); break;
-        case 3: chunk_trace2<N, 1>(Q, gR, EN3, (int64_t)(eyp + fel) * N3, pt, lmr, lfm, qnb[u], gnb[u]); break;
-        case 4: chunk_trace2<N, 2>(Q, gR, EN3, (int64_t)(ezm + fel) * N3, pt, lpr, lfp, qnb[u], gnb[u]); break;
-        default: chunk_trace2<N, 2>(Q, gR, EN3, (int64_t)(ezp + fel) * N3, pt, lmr, lfm, qnb[u], gnb[u]); break;
+      if constexpr (N == 4) {
+        // partner-lane pairs (lanes of a pair share fel, FP is even)
+        switch (S::face(s)) {   // uniform over the wave; neighbour's face on the other side
+          case 2: chunk_trace2_x2<N, 1>(Q, gR, EN3, (int64_t)(eym + fel) * N3, pt, lpr, lfp, qnb[u], gnb[u]); break;
+          case 3: chunk_trace2_x2<N, 1>(Q, gR, EN3, (int64_t)(eyp + fel) * N3, pt, lmr, lfm, qnb[u], gnb[u]); break;
+          case 4: chunk_trace2_x2<N, 2>(Q, gR, EN3, (int64_t)(ezm + fel) * N3, pt, lpr, lfp, qnb[u], gnb[u]); break;
+          default: chunk_trace2_x2<N, 2>(Q, gR, EN3, (int64_t)(ezp + fel) * N3, pt, lmr, lfm, qnb[u], gnb[u]); break;
+        }
+      } else {
+        switch (S::face(s)) {   // uniform over the wave; neighbour's face on the other side
+          case 2: chunk_trace2<N, 1>(Q, gR, EN3, (int64_t)(eym + fel) * N3, pt, lpr, lfp, qnb[u], gnb[u]); break;
+          case 3: chunk_trace2<N, 1>(Q, gR, EN3, (int64_t)(eyp + fel) * N3, pt, lmr, lfm, qnb[u], gnb[u]); break;
+          case 4: chunk_trace2<N, 2>(Q, gR, EN3, (int64_t)(ezm + fel) * N3, pt, lpr, lfp, qnb[u], gnb[u]); break;
+          default: chunk_trace2<N, 2>(Q, gR, EN3, (int64_t)(ezp + fel) * N3, pt, lmr, lfm, qnb[u], gnb[u]); break;
+        }
       }
     } else {
 #pragma unroll
