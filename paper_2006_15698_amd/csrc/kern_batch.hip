@@ -40,7 +40,9 @@ constexpr int kSmem64 = arrmax(kSizes64, sizeof(kSizes64) / sizeof(int));       
 constexpr int kSmem32 = (arrmax(kSizes32, sizeof(kSizes32) / sizeof(int)) + 7) / 8;  // doubles
 
 // How the FP64 variants read their y/z neighbour lines: partner-lane pairs
-// at even N, LDS-handed pairs at odd N.
+// at even N, LDS-handed pairs at odd N.  The FP32 variants read one point
+// per lane: partner-lane pairs would take their union of registers from
+// three waves per SIMD to two.
 template <int N>
 constexpr int kLines64 = N % 2 == 0 ? dgdev::LINES_DPP : dgdev::LINES_LDS;
 
@@ -56,12 +58,12 @@ __device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, const dou
   // items are row-aligned blocks: the last block of a row may be short
   const int x0 = e0 % I.tab.nx;
   const int ne = dgdev::imin(I.epb, I.tab.nx - x0);
-#define DG_CASE(n, e)                                                                                        \
-  case n * 64 + e:                                                                                           \
-    if (F32)                                                                                                 \
-      dgdev::stage_nb32_body<n, MODE, e, BNT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid);       \
-    else                                                                                                     \
-      dgdev::stage_nb_body<n, MODE, e, BNT, kLines64<n>>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid); \
+#define DG_CASE(n, e)                                                                                                       \
+  case n * 64 + e:                                                                                                          \
+    if (F32)                                                                                                                \
+      dgdev::stage_nb32_body<n, MODE, e, BNT, dgdev::LINES_POINT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid); \
+    else                                                                                                                    \
+      dgdev::stage_nb_body<n, MODE, e, BNT, kLines64<n>>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem, tid);          \
     break;
   switch (key) { DG_BATCH_VARIANTS(DG_CASE) default: break; }
 #undef DG_CASE

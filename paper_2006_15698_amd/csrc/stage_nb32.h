@@ -54,6 +54,42 @@ __device__ __forceinline__ void chunk_trace32(const double* __restrict__ base, i
   }
 }
 
+// chunk_trace32 for even N by partner-lane pairs (as chunk_trace_x2 in
+// stage_nb.h): each lane loads the line-node pair of its point and its
+// x-neighbour at m = 2j + (pt & 1) and takes the other m from its partner by
+// DPP.  Same anchor, conversions and FMA chain as chunk_trace32.  Both lanes
+// of a pair must be active.
+template <int N, int D, int SIDE>
+__device__ __forceinline__ void chunk_trace32_x2(const double* __restrict__ base, int64_t EN3, int fel, int pt,
+                                                 const float* lmr, const float* lpr, double* out) {
+  static_assert(N % 2 == 0, "pairs of x-adjacent points need an even N");
+  constexpr int N3 = N * N * N;
+  const int s = pt & 1;
+  const int pe = pt - s;
+  double2 w[5][N / 2];
+  double an[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double* qn = base + f * EN3 + fel * N3;
+    an[f] = qn[0];
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j)
+      __builtin_memcpy(&w[f][j], qn + (s ? tnode<N>(D, 2 * j + 1, pe) : tnode<N>(D, 2 * j, pe)), 16);
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double a = an[f];
+    float v = 0.0f;
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const double px = swap_adjacent(w[f][j].x), py = swap_adjacent(w[f][j].y);
+      v = fmaf(SIDE ? lmr[2 * j] : lpr[2 * j], (float)((s ? py : w[f][j].x) - a), v);
+      v = fmaf(SIDE ? lmr[2 * j + 1] : lpr[2 * j + 1], (float)((s ? w[f][j].y : px) - a), v);
+    }
+    out[f] = a + (double)v;
+  }
+}
+
 // FP32 deviation sum along the line of point pt in direction D of an
 // element whose deviations are at `dev` (LDS, field stride NH).
 template <int N, int D>
@@ -85,8 +121,10 @@ __device__ __forceinline__ void face_flux32(const float* sD, const double* sAnc,
 
 // Elements [e0, e0 + ne) of one x-row, ne <= EPB.  MODE 0: RR = dQ/dt.
 // MODE 1: RK stage (res = RR in place).  MODE 2: the first RK stage (a = 0:
-// res written, not read).  smem: Nb32Smem<N,EPB>::bytes.
-template <int N, int MODE, int EPB, int NT>
+// res written, not read).  NBL: LINES_DPP reads the y/z neighbour lines
+// by partner-lane pairs (even N), anything else one point per lane.  smem:
+// Nb32Smem<N,EPB>::bytes.
+template <int N, int MODE, int EPB, int NT, int NBL>
 __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double* __restrict__ Qin,
                                                 double* __restrict__ Qout, double* __restrict__ RR, double rka,
                                                 double rkb, double dt, int first, int e0, int ne, double* smem,
@@ -166,11 +204,23 @@ __device__ __forceinline__ void stage_nb32_body(const DGTables& tb, const double
     const int i = (s < S::NYZ ? S::chunk(s) : 0) * 64 + lane;
     const int fel = i / N2, pt = i - fel * N2;
     if (s < S::NYZ && i < FP && fel < ne) {
-      switch (S::face(s)) {   // uniform over the wave
-        case 2: chunk_trace32<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-        case 3: chunk_trace32<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-        case 4: chunk_trace32<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
-        default: chunk_trace32<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+      if constexpr (NBL == LINES_DPP) {
+        static_assert(N % 2 == 0, "partner-lane pairs need an even N");
+        // (pairs of lanes share fel, and FP is even: both lanes of a pair
+        // take this branch or neither)
+        switch (S::face(s)) {   // uniform over the wave
+          case 2: chunk_trace32_x2<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          case 3: chunk_trace32_x2<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          case 4: chunk_trace32_x2<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          default: chunk_trace32_x2<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+        }
+      } else {
+        switch (S::face(s)) {   // uniform over the wave
+          case 2: chunk_trace32<N, 1, 0>(Qin + (int64_t)eym * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          case 3: chunk_trace32<N, 1, 1>(Qin + (int64_t)eyp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          case 4: chunk_trace32<N, 2, 0>(Qin + (int64_t)ezm * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+          default: chunk_trace32<N, 2, 1>(Qin + (int64_t)ezp * N3, EN3, fel, pt, lmr, lpr, nb[u]); break;
+        }
       }
     } else {
       nb[u][0] = 1.0; nb[u][1] = 0.0; nb[u][2] = 0.0; nb[u][3] = 0.0; nb[u][4] = 2.5;
