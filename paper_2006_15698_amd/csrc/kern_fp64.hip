@@ -53,13 +53,14 @@ k_stage(DGTables tb, double* __restrict__ Q, double* __restrict__ RR,
 
 // How the single-mesh stage reads its y/z neighbour lines: partner-lane
 // pairs at N = 2, 4, 6 (against one point per lane: N=6 10% faster, N=4
-// 6% beyond the MALL and even at 32^3, N=2 1-2%); LDS-handed pairs at
-// N = 7, where they are 8% faster (at N = 4, 5, 6 and 8 they were even or
-// 2-7% slower); one point per lane at N = 3, 5 and 8 (partner-lane pairs
-// take N = 8 past 128 registers).
+// 6% beyond the MALL and even at 32^3, N=2 1-2%) and, on the row-pair
+// layout, at N = 5 (2.5% at 40^3 and 48^3); LDS-handed pairs at N = 7,
+// where they are 8% faster (at N = 4, 5, 6 and 8 they were even or 2-7%
+// slower); one point per lane at N = 3 and 8 (partner-lane pairs take
+// N = 8 past 128 registers).
 template <int N>
 constexpr int kLines = N == 7 ? dgdev::LINES_LDS
-                               : (N % 2 == 0 && N <= 6) ? dgdev::LINES_DPP : dgdev::LINES_POINT;
+                               : ((N % 2 == 0 && N <= 6) || N == 5) ? dgdev::LINES_DPP : dgdev::LINES_POINT;
 
 // Neighbour-read variant: Qin -> Qout (different buffers), no trace buffers;
 // element blocks visited in the order `ord`.  At N=4 the bound holds the

@@ -150,6 +150,69 @@ __device__ __forceinline__ void chunk_trace_x2(const double* __restrict__ base, 
   }
 }
 
+// Row-pair lane layout for odd N: each row b of a face chunk element takes
+// N + 1 lanes, c = 0..N, so that lanes 2k and 2k + 1 always hold two
+// x-adjacent points a = c of one row; lane c = N is a phantom that only
+// loads for its partner.  The last pair of a row (c = N - 1, N) reads the
+// node pair starting at a = N - 2, so every pair stays inside its row.
+template <int N, int EPB>
+struct RowPairLane {
+  static constexpr int RL = N + 1;
+  static constexpr int LANES = EPB * N * RL;
+  int fel, b, c;
+  bool in;
+  __host__ __device__ explicit RowPairLane(int lane) {
+    in = lane < LANES;
+    fel = lane / (N * RL);
+    const int r = lane - fel * (N * RL);
+    b = r / RL;
+    c = r - b * RL;
+  }
+  // first point of the node pair this lane loads, and which of the two is its own
+  __host__ __device__ int pair_start() const { return ((c & ~1) < N - 1 ? (c & ~1) : N - 2) + N * b; }
+  __host__ __device__ int own() const { return (c < N ? c : N - 1) + N * b - pair_start(); }
+};
+
+// chunk_trace for odd N on the row-pair layout: each lane loads the node
+// pair of its row pair at m = 2j + (c & 1) (j < (N - 1) / 2) and at
+// m = N - 1, takes its value at the other m of each two from its partner by
+// DPP, and keeps its own half of the pair.  Same FMA chain as chunk_trace.
+// Both lanes of a pair must be active.
+template <int N, int EPB, int D, int SIDE>
+__device__ __forceinline__ void chunk_trace_rp(const double* __restrict__ base, int64_t EN3,
+                                               const RowPairLane<N, EPB>& rp, const double* lmr,
+                                               const double* lpr, double* out) {
+  static_assert(N % 2 == 1, "the row-pair layout is for odd N");
+  constexpr int N3 = N * N * N, J = (N - 1) / 2;
+  const int s = rp.c & 1;
+  const int p0 = rp.pair_start();
+  const int k = rp.own();
+  double2 w[5][J + 1];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double* qn = base + f * EN3 + rp.fel * N3 + tnode<N>(D, 0, p0);
+#pragma unroll
+    for (int j = 0; j <= J; ++j) {
+      const int m = j < J ? 2 * j + s : N - 1;
+      __builtin_memcpy(&w[f][j], qn + (tnode<N>(D, m, p0) - tnode<N>(D, 0, p0)), 16);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const double px = swap_adjacent(w[f][j].x), py = swap_adjacent(w[f][j].y);
+      const double mine = k ? w[f][j].y : w[f][j].x;     // own point at m = 2j + s
+      const double other = k ? py : px;                   // own point at the partner's m
+      v = fma(SIDE ? lmr[2 * j] : lpr[2 * j], s ? other : mine, v);
+      v = fma(SIDE ? lmr[2 * j + 1] : lpr[2 * j + 1], s ? mine : other, v);
+    }
+    v = fma(SIDE ? lmr[N - 1] : lpr[N - 1], k ? w[f][J].y : w[f][J].x, v);
+    out[f] = v;
+  }
+}
+
 // Paired neighbour lines.  On a y- or z-face, the line nodes of two face
 // points next to each other along x (tangential index a, a + 1 of one row b)
 // are next to each other in memory for every m, so one 16-byte load brings
@@ -358,7 +421,11 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
   }
   const int wave = tid >> 6, lane = tid & 63;
   constexpr bool PON = LINES == LINES_LDS && PairLines<N, EPB, NW>::on;
-  static_assert(LINES != LINES_DPP || N % 2 == 0, "partner-lane pairs need an even N");
+  // partner-lane pairs: on the point layout at even N, on the row-pair
+  // layout at odd N (y/z slots only; one slot per face, one per wave)
+  constexpr bool RP = LINES == LINES_DPP && N % 2 == 1;
+  static_assert(!RP || (RowPairLane<N, EPB>::LANES <= 64 && S::NYZ == 4 && NW >= 4),
+                "row pairs need one wave per y/z face");
   using PL = PairLines<N, EPB, NW>;
   double nb[PON ? 1 : RNDG][5];
   if constexpr (PON) {
@@ -379,8 +446,19 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
       const int s = wave + u * NW;
       const int i = (s < S::NYZ ? S::chunk(s) : 0) * 64 + lane;
       const int fel = i / N2, pt = i - fel * N2;
-      if (s < S::NYZ && i < FP && fel < ne) {
-        if constexpr (LINES == LINES_DPP) {
+      const RowPairLane<N, EPB> rp(lane);
+      if (RP && s < S::NYZ && rp.in && rp.fel < ne) {
+        if constexpr (RP) {
+          // (the two lanes of a pair share fel, and LANES is even)
+          switch (S::face(s)) {   // uniform over the wave
+            case 2: chunk_trace_rp<N, EPB, 1, 0>(Qin + (int64_t)eym * N3, EN3, rp, lmr, lpr, nb[u]); break;
+            case 3: chunk_trace_rp<N, EPB, 1, 1>(Qin + (int64_t)eyp * N3, EN3, rp, lmr, lpr, nb[u]); break;
+            case 4: chunk_trace_rp<N, EPB, 2, 0>(Qin + (int64_t)ezm * N3, EN3, rp, lmr, lpr, nb[u]); break;
+            default: chunk_trace_rp<N, EPB, 2, 1>(Qin + (int64_t)ezp * N3, EN3, rp, lmr, lpr, nb[u]); break;
+          }
+        }
+      } else if (!RP && s < S::NYZ && i < FP && fel < ne) {
+        if constexpr (LINES == LINES_DPP && N % 2 == 0) {
           // (pairs of lanes share fel, and FP is even: both lanes of a pair
           // take this branch or neither)
           switch (S::face(s)) {   // uniform over the wave
@@ -446,8 +524,17 @@ __device__ __forceinline__ void stage_nb_body(const DGTables& tb, const double* 
 #pragma unroll
   for (int u = 0; u < RND; ++u) {
     const int s = wave + u * NW;
-    const int i = (s < S::NS ? S::chunk(s) : 0) * 64 + lane;
-    if (s < S::NS && i < FP) {
+    int i = (s < S::NS ? S::chunk(s) : 0) * 64 + lane;
+    bool live = s < S::NS && i < FP;
+    if constexpr (RP) {
+      // y/z slots keep the row-pair layout of their neighbour traces
+      if (s < S::NYZ) {
+        const RowPairLane<N, EPB> rp(lane);
+        live = rp.in && rp.c < N;
+        i = rp.fel * N2 + rp.b * N + rp.c;
+      }
+    }
+    if (live) {
       const int face = S::face(s);
       const int fel = i / N2, pt = i - fel * N2;
       const double* own = sQ + (fel + 1) * N3;

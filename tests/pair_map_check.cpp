@@ -79,8 +79,67 @@ static int check_x2() {
   return 0;
 }
 
+// Row-pair layout (RowPairLane, odd N): lanes 2k and 2k + 1 share element
+// and row and load the same node pair, which lies in that row; the real
+// lanes (c < N) cover every point of the face chunk exactly once, each
+// owning one half of its pair; and the pair's line nodes are neighbours in
+// memory inside the element for every m.
+template <int N, int EPB>
+static int check_rp() {
+  using RP = dgdev::RowPairLane<N, EPB>;
+  constexpr int N2 = N * N, N3 = N2 * N;
+  if (RP::LANES > 64 || RP::LANES % 2 != 0) {
+    printf("N=%d EPB=%d: row-pair layout does not fit a wave\n", N, EPB);
+    return 1;
+  }
+  std::vector<int> hits(EPB * N2, 0);
+  for (int lane = 0; lane < RP::LANES; lane += 2) {
+    const RP p0(lane), p1(lane + 1);
+    if (!p0.in || !p1.in || p0.fel != p1.fel || p0.b != p1.b || p0.pair_start() != p1.pair_start()) {
+      printf("N=%d EPB=%d lanes %d, %d: not one pair\n", N, EPB, lane, lane + 1);
+      return 1;
+    }
+    const int ps = p0.pair_start();
+    if (ps - N * p0.b < 0 || ps - N * p0.b + 1 >= N) {
+      printf("N=%d EPB=%d lane %d: pair leaves its row\n", N, EPB, lane);
+      return 1;
+    }
+    for (int d = 1; d <= 2; ++d) {
+      for (int m = 0; m < N; ++m) {
+        const int n0 = d == 1 ? dgdev::tnode<N>(1, m, ps) : dgdev::tnode<N>(2, m, ps);
+        const int n1 = d == 1 ? dgdev::tnode<N>(1, m, ps + 1) : dgdev::tnode<N>(2, m, ps + 1);
+        if (n1 != n0 + 1 || n0 < 0 || n1 >= N3) {
+          printf("N=%d EPB=%d d=%d lane %d m %d: nodes not adjacent\n", N, EPB, d, lane, m);
+          return 1;
+        }
+      }
+    }
+    for (const RP* p : {&p0, &p1}) {
+      if (p->own() < 0 || p->own() > 1) {
+        printf("N=%d EPB=%d: own half out of range\n", N, EPB);
+        return 1;
+      }
+      if (p->c < N) {
+        if (ps + p->own() != p->c + N * p->b) {
+          printf("N=%d EPB=%d: lane's own half is not its point\n", N, EPB);
+          return 1;
+        }
+        hits[p->fel * N2 + p->c + N * p->b] += 1;
+      }
+    }
+  }
+  for (int i = 0; i < EPB * N2; ++i) {
+    if (hits[i] != 1) {
+      printf("N=%d EPB=%d: point %d covered %d times\n", N, EPB, i, hits[i]);
+      return 1;
+    }
+  }
+  return 0;
+}
+
 int main() {
   int bad = 0;
+  bad |= check_rp<5, 2>() | check_rp<5, 1>() | check_rp<7, 1>() | check_rp<3, 4>();
   bad |= check_x2<2>() | check_x2<4>() | check_x2<6>() | check_x2<8>();
   // single-mesh kernels (degree, elements per block, threads)
   bad |= check<2, 16, 128>() | check<3, 9, 256>() | check<4, 4, 256>() | check<5, 2, 256>();
