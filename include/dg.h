@@ -24,7 +24,9 @@
  *     [ex hx,(ex+1)hx] x [ey hy,(ey+1)hy] x [ez hz,(ez+1)hz], h_d = L_d/n_d;
  *     node (i,j,k) sits at the Gauss-Legendre points (xi_i, xi_j, xi_k) of
  *     that box.  Neighbours are periodic.
- *   Ownership.  The caller owns every array and the workspace (allocated by
+ *   Alignment.  State arrays must be 8-byte aligned, as any array of doubles
+     is (DG_EINVAL otherwise): the kernels read them in 8- and 16-byte pieces.
+   Ownership.  The caller owns every array and the workspace (allocated by
  *     PyTorch or hipMalloc); the library owns only the context.  The library
  *     performs no device allocation.
  *   Streams.  Every call runs asynchronously on the context's stream (default

@@ -280,6 +280,7 @@ int dg_batch_rhs(dg_batch* b, const double* Q, double* R) {
   int rc = ready(b);
   if (rc) return rc;
   if (!Q || !R) return dg_set_error(DG_EINVAL, "NULL array");
+  if (((uintptr_t)Q | (uintptr_t)R) & 7) return dg_set_error(DG_EINVAL, "arrays must be 8-byte aligned");
   const size_t sb = (size_t)b->qoff[b->count] * sizeof(double);
   if ((const char*)Q < (const char*)R + sb && (const char*)R < (const char*)Q + sb)
     return dg_set_error(DG_EALIAS, "R overlaps Q");
@@ -293,6 +294,7 @@ int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps) {
   int rc = ready(b);
   if (rc) return rc;
   if (!Q || !res) return dg_set_error(DG_EINVAL, "NULL array");
+  if (((uintptr_t)Q | (uintptr_t)res) & 7) return dg_set_error(DG_EINVAL, "arrays must be 8-byte aligned");
   if (nsteps < 0) return dg_set_error(DG_EINVAL, "nsteps must be >= 0");
   const size_t sb = (size_t)b->qoff[b->count] * sizeof(double);
   if ((char*)Q < (char*)res + sb && (char*)res < (char*)Q + sb) return dg_set_error(DG_EALIAS, "res overlaps Q");
@@ -313,6 +315,7 @@ int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps) {
   int rc = ready(b);
   if (rc) return rc;
   if (!Q || !res) return dg_set_error(DG_EINVAL, "NULL array");
+  if (((uintptr_t)Q | (uintptr_t)res) & 7) return dg_set_error(DG_EINVAL, "arrays must be 8-byte aligned");
   if (nsteps < 0) return dg_set_error(DG_EINVAL, "nsteps must be >= 0");
   const size_t sb = (size_t)b->qoff[b->count] * sizeof(double);
   if ((char*)Q < (char*)res + sb && (char*)res < (char*)Q + sb) return dg_set_error(DG_EALIAS, "res overlaps Q");

@@ -143,6 +143,10 @@ bool overlap(const void* a, const void* b, size_t bytes) {
   return pa < pb + bytes && pb < pa + bytes;
 }
 
+// State arrays are arrays of doubles: the kernels read them in 8- and
+// 16-byte pieces at 8-byte alignment.
+bool misaligned(const void* p) { return ((uintptr_t)p & 7) != 0; }
+
 int check_ready(dg_ctx* c) {
   if (!c) return fail(DG_EINVAL, "NULL context");
   const DGWorkspace L = dg_workspace_layout(c);
@@ -162,6 +166,7 @@ int run_reduce(dg_ctx* c, const double* Q, double out[DG_RED_VALS]) {
   int rc = check_ready(c);
   if (rc) return rc;
   if (!Q) return fail(DG_EINVAL, "NULL state");
+  if (misaligned(Q)) return fail(DG_EINVAL, "state is not 8-byte aligned");
   const DGWorkspace L = dg_workspace_layout(c);
   double* red = (double*)(c->ws + L.off_red);
   int err = timed(c, TK_RED, [&] { return dg_launch_reduce(c, Q, red); });
@@ -221,6 +226,7 @@ int stages(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
 
 int check_state_pair(dg_ctx* c, const void* a, const char* an, const void* b, const char* bn) {
   if (!a || !b) return fail(DG_EINVAL, "NULL %s", !a ? an : bn);
+  if (misaligned(a) || misaligned(b)) return fail(DG_EINVAL, "%s is not 8-byte aligned", misaligned(a) ? an : bn);
   if (overlap(a, b, state_bytes(c))) return fail(DG_EALIAS, "%s overlaps %s", an, bn);
   return DG_OK;
 }
@@ -658,6 +664,7 @@ int dg_rhs_vjp(dg_ctx* c, const double* Q, const double* gR, double* gQ) {
   int rc = check_ready(c);
   if (rc) return rc;
   if (!Q || !gR || !gQ) return fail(DG_EINVAL, "NULL array");
+  if (misaligned(Q) || misaligned(gR) || misaligned(gQ)) return fail(DG_EINVAL, "arrays must be 8-byte aligned");
   if (overlap(Q, gQ, state_bytes(c))) return fail(DG_EALIAS, "gQ overlaps Q");
   if (overlap(gR, gQ, state_bytes(c))) return fail(DG_EALIAS, "gQ overlaps gR");
   int err = timed(c, TK_VJP, [&] { return dg_launch_vjp(c, Q, gR, gQ, c->ws); });
@@ -671,6 +678,7 @@ int dg_rk_stage_vjp(dg_ctx* c, int s, const double* Qs, double* gQ, double* gres
   if (s < 0 || s > 4) return fail(DG_EINVAL, "stage must be 0..4 (got %d)", s);
   if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
   if (!Qs || !gQ || !gres) return fail(DG_EINVAL, "NULL array");
+  if (misaligned(Qs) || misaligned(gQ) || misaligned(gres)) return fail(DG_EINVAL, "arrays must be 8-byte aligned");
   const size_t sb = state_bytes(c);
   if (overlap(gQ, gres, sb)) return fail(DG_EALIAS, "gQ overlaps gres");
   if (overlap(Qs, gQ, sb) || overlap(Qs, gres, sb)) return fail(DG_EALIAS, "adjoint overlaps Qs");

@@ -88,6 +88,11 @@ def test_argument_errors_before_any_launch(dg):
         assert lib.dg_rk_step(ctx, Q, Q + 8, ctypes.c_double(1e-3)) == dg.DG_EALIAS
         assert lib.dg_rhs_vjp(ctx, Q, R, Q) == dg.DG_EALIAS
         assert lib.dg_rhs_vjp(ctx, Q, R, R) == dg.DG_EALIAS
+        # misaligned (not a multiple of 8 bytes)
+        assert lib.dg_rhs(ctx, Q + 4, R) == dg.DG_EINVAL
+        assert lib.dg_rk_step(ctx, Q, R + 4, ctypes.c_double(1e-3)) == dg.DG_EINVAL
+        assert lib.dg_rhs_vjp(ctx, Q, R + 4, 0x40000000) == dg.DG_EINVAL
+        assert lib.dg_rk_stage_vjp(ctx, 1, Q, R, 0x40000004, ctypes.c_double(1e-3)) == dg.DG_EINVAL
         # NULL
         assert lib.dg_rhs(ctx, None, R) == dg.DG_EINVAL
         assert lib.dg_rhs(ctx, Q, None) == dg.DG_EINVAL
