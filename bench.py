@@ -56,14 +56,21 @@ def flops_per_dof_stage(N):
     return 38 + 30 * N + 3 * (40 * N + 76) / N + 30
 
 
-# The sources each measured stage kernel is built from (neighbour-read form,
-# its tables and launch parameters), per precision.
-_COMMON_SOURCES = ["include/dg.h", "paper_2006_15698_amd/csrc/dg_internal.h",
+# The device sources each measured kernel is built from (the C ABI header
+# only declares host entry points), per kernel family: the
+# single-mesh stage kernel in either precision (neighbour-read form, its
+# tables and launch parameters), the batched persistent kernel and the
+# neighbour-read adjoint kernel.
+_COMMON_SOURCES = ["paper_2006_15698_amd/csrc/dg_internal.h",
                    "paper_2006_15698_amd/csrc/stage_fp64.h", "paper_2006_15698_amd/csrc/stage_nb.h"]
+_FP32_SOURCES = ["paper_2006_15698_amd/csrc/stage_fp32.h", "paper_2006_15698_amd/csrc/stage_nb32.h"]
 STAGE_SOURCES = {
     "fp64": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_fp64.hip"],
-    "fp32": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/stage_fp32.h", "paper_2006_15698_amd/csrc/stage_nb32.h",
-                               "paper_2006_15698_amd/csrc/kern_fp32.hip"],
+    "fp32": _COMMON_SOURCES + _FP32_SOURCES + ["paper_2006_15698_amd/csrc/kern_fp32.hip"],
+    "batch": _COMMON_SOURCES + _FP32_SOURCES + ["paper_2006_15698_amd/csrc/dg_batch.h",
+                                                "paper_2006_15698_amd/csrc/kern_batch.hip",
+                                                "paper_2006_15698_amd/csrc/batch_api.cpp"],
+    "vjp": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_vjp.hip"],
 }
 
 
@@ -76,28 +83,28 @@ def _code_only(text):
     return " ".join(text.split())
 
 
-def kernel_source_hash(precision="fp64"):
-    """Hash of the stage kernel's code: counters taken on other code are
+def kernel_source_hash(family="fp64"):
+    """Hash of a kernel family's code: counters taken on other code are
     stale."""
     h = hashlib.sha256()
-    for f in STAGE_SOURCES[precision]:
+    for f in STAGE_SOURCES[family]:
         with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, options):
-    """HBM bytes per launch of the stage kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source with the
-    same options."""
+def measured_traffic(workload, family, options):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    (family as in STAGE_SOURCES) with the same options."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    ent = rec.get(f"{workload}:{precision}")
-    if not ent or ent.get("kernel_src") != kernel_source_hash(precision) or ent.get("options") != options:
+    ent = rec.get(f"{workload}:{family}")
+    if not ent or ent.get("kernel_src") != kernel_source_hash(family) or ent.get("options") != options:
         return None
     return ent.get("bytes_per_launch")
 
@@ -134,6 +141,97 @@ def cpu_baseline(n, p, L, budget_s):
                       f"BLAS threads {threads}, host cpu_count {os.cpu_count()}"}
 
 
+GOLDEN_48 = os.path.join(ROOT, "tests", "golden", "tgv48_p4_50steps.npz")
+
+
+def _errors_vs_stored_oracle(Qf, Q0, golden):
+    """L2 error of a GPU state after the stored run's steps against the
+    oracle's state, on the stored sampled elements (all nodes and fields):
+    relative to the oracle state and to the oracle's change over the run,
+    overall and per field."""
+    import numpy as np
+    import torch
+    ex, ey, ez = (torch.from_numpy(c).to(Qf.device) for c in golden["elems"].T)
+    got = Qf[:, ez, ey, ex].cpu().numpy()
+    start = Q0[:, ez, ey, ex].cpu().numpy()
+    ref = golden["samples"]
+    d = (got - ref).reshape(5, -1)
+    ch = (ref - start).reshape(5, -1)
+    rf = ref.reshape(5, -1)
+    return {"l2_rel_state": float(np.linalg.norm(d) / np.linalg.norm(rf)),
+            "l2_rel_change": float(np.linalg.norm(d) / np.linalg.norm(ch)),
+            "l2_rel_change_per_field": [float(v) for v in np.linalg.norm(d, axis=1) / np.linalg.norm(ch, axis=1)]}
+
+
+def precision_clause(args, n, p, L, Q0, dt, K, Wm, graph, value):
+    """The FP32 matrix-core form against the plain FP64 form on the same GPU:
+    the other form's rate over the same Wm + K steps and its stage kernel's
+    average launch, the speedup of FP32 over FP64, and the L2 error of both
+    forms against the FP64 oracle after the stored oracle run's 50 steps
+    from the initial state (48^3 p=4 only; other workloads report the L2
+    difference between the two forms after the timed steps)."""
+    import numpy as np
+    import torch
+    from paper_2006_15698_amd import dg
+
+    primary = args.precision
+    other = "fp32" if primary == "fp64" else "fp64"
+    mode = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32_MFMA}
+    so = dg.Solver((n, n, n), p, L=L, precision=mode[other])
+    Qo = Q0.clone()
+    ro = torch.zeros_like(Qo)
+    if Wm > 0:
+        so.step(Qo, ro, dt, nsteps=Wm, graph=graph)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    so.step(Qo, ro, dt, nsteps=K, graph=graph)
+    ev1.record()
+    torch.cuda.synchronize()
+    v_other = n ** 3 * (p + 1) ** 3 * 5 * K / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    dg.dg_set_timing(so.ctx, True)
+    so.step(Qo, ro, dt, nsteps=K)
+    t = dg.dg_timing_read(so.ctx)
+    dg.dg_set_timing(so.ctx, False)
+    rates = {primary: value, other: v_other}
+    out = {"fp32_value": rates["fp32"], "fp64_value": rates["fp64"], "unit": "GDOF-RK-stages/sec",
+           "speedup_fp32_over_fp64": rates["fp32"] / rates["fp64"],
+           "steps_timed": K,
+           f"{other}_stage_kernel_avg_us": t["stage"][0] / t["stage"][1] * 1e3}
+    if args.workload == "tgv48_p4" and os.path.exists(GOLDEN_48):
+        golden = dict(np.load(GOLDEN_48, allow_pickle=False))
+        gdt, steps = float(golden["dt"]), int(golden["steps"])
+        errs = {}
+        for form in ("fp64", "fp32"):
+            sf = so if form == other else dg.Solver((n, n, n), p, L=L, precision=mode[form])
+            Qf = Q0.clone()
+            rf = torch.zeros_like(Qf)
+            sf.step(Qf, rf, gdt, nsteps=steps)
+            torch.cuda.synchronize()
+            errs[form] = _errors_vs_stored_oracle(Qf, Q0, golden)
+            del Qf, rf
+        out["l2_err_vs_oracle"] = errs
+        out["error_run"] = (f"{steps} LSERK45 steps from the initial state at the oracle run's dt {gdt:.6e}, "
+                            f"untimed; L2 over {golden['elems'].shape[0]} seeded sampled elements "
+                            f"(all nodes, all fields) against the stored FP64 oracle state "
+                            f"(tests/golden/tgv48_p4_50steps.npz)")
+    else:
+        fin = {}
+        for form in ("fp64", "fp32"):
+            sf = so if form == other else dg.Solver((n, n, n), p, L=L, precision=mode[form])
+            Qf = Q0.clone()
+            rf = torch.zeros_like(Qf)
+            sf.step(Qf, rf, dt, nsteps=K)
+            fin[form] = Qf
+        diff = float(torch.linalg.vector_norm(fin["fp32"] - fin["fp64"]))
+        out["l2_diff_between_forms"] = {
+            "rel_state": diff / float(torch.linalg.vector_norm(fin["fp64"])),
+            "rel_change": diff / float(torch.linalg.vector_norm(fin["fp64"] - Q0)), "steps": K,
+            "note": "no stored oracle run for this workload: FP32 form against the GPU's FP64 form"}
+    return out
+
+
 def run_adjoint(args):
     """The adjoint configuration: K whole gradients (forward 40 steps storing
     Q every 8, then per segment recompute the stage inputs and run the stages
@@ -167,18 +265,23 @@ def run_adjoint(args):
     dof = s.num_dof
     value = dof * 5 * nsteps / (ms * 1e-3) / 1e9
 
-    def vjp_rate(solver, Q):
+    def vjp_rate(solver, Q, reps=20):
+        """Average duration of dg_rhs_vjp: HIP events on the stream the
+        kernel runs on (torch's current stream) around ``reps`` back-to-back
+        calls, after three warm-up calls."""
         gR = torch.randn_like(Q)
         out = torch.empty_like(Q)
         for _ in range(3):
             solver.rhs_vjp(Q, gR, out)
-        dg.dg_set_timing(solver.ctx, True)
-        for _ in range(20):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
             solver.rhs_vjp(Q, gR, out)
-        t = dg.dg_timing_read(solver.ctx)
-        dg.dg_set_timing(solver.ctx, False)
-        v_ms, v_n = t["vjp"]
-        avg_s = v_ms / v_n * 1e-3
+        b.record()
+        torch.cuda.synchronize()
+        avg_s = a.elapsed_time(b) / reps * 1e-3
         nd = solver.num_dof
         return avg_s, 120 * nd / avg_s / 1e9
 
@@ -192,7 +295,8 @@ def run_adjoint(args):
         "config": {"workload": f"adjoint16_p3: {desc}", "elements": n ** 3, "p": p, "dof": dof, "rk_steps": nsteps,
                    "checkpoint_every": 8, "dt": dt},
         "roofline": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": gbs32 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("tgv32_p3", "vjp", s32.options()),
                      "kernel": "k_vjp_nb (dg_rhs_vjp) on TGV 32^3 p=3",
                      "avg_launch_us": avg32 * 1e6, "alg_bytes_per_launch": 120 * s32.num_dof,
                      "at_16p3": {"avg_launch_us": avg16 * 1e6, "achieved": gbs16}},
@@ -256,7 +360,10 @@ def run_batch(args):
         "config": {"workload": f"batch512: {desc}", "meshes": len(specs), "dof": dof,
                    "meshes_per_degree": degs, "tiles": b.tiles, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("batch512", "batch", {"precision": args.precision,
+                                                                       "tiles": {str(k): v for k, v in
+                                                                                 sorted(b.tiles.items())}}),
                      "kernel": "k_batch_stage (persistent, all meshes)", "avg_launch_us": avg_s * 1e6,
                      "alg_bytes_per_launch": ALG_BYTES_PER_DOF_STAGE * dof},
     }
@@ -267,11 +374,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="tgv32_p3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="tgv48_p4", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-precision-clause", action="store_true",
+                    help="skip the FP32-form rate and both forms' errors against the oracle")
     ap.add_argument("--exchange", default="neighbour", choices=["neighbour", "traces"],
                     help="how a stage obtains its neighbours' face traces (FP64 path)")
     ap.add_argument("--xcd-remap", type=int, default=None, choices=[0, 1],
@@ -357,7 +466,6 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     value = dof * 5 * K / (ms * 1e-3) / 1e9
-    Qrun = Q.clone() if args.precision == "fp32" else None   # state after Wm + K steps
 
     out = {
         "metric": "GDOF-RK-stages/sec",
@@ -409,29 +517,8 @@ def main():
                             "frac": fl / avg_s / 1e12 / FP64_PEAK_TFS,
                             "flops_per_dof_stage": flops_per_dof_stage(p + 1)}
 
-    if Qrun is not None:
-        # The FP32 form against the FP64 form on the same GPU: FP64 throughput
-        # measured the same way, and the L2 difference of the two states
-        # after the same Wm + K steps (the FP64 path equals the oracle to
-        # 1e-12 per RHS).
-        s64 = dg.Solver((n, n, n), p, L=L, precision=dg.DG_FP64)
-        Q64 = Q0.clone()
-        r64 = torch.zeros_like(Q64)
-        if Wm > 0:
-            s64.step(Q64, r64, dt, nsteps=Wm, graph=graph)
-        torch.cuda.synchronize()
-        ev0.record()
-        s64.step(Q64, r64, dt, nsteps=K, graph=graph)
-        ev1.record()
-        torch.cuda.synchronize()
-        v64 = dof * 5 * K / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
-        diff = float(torch.linalg.vector_norm(Qrun - Q64))
-        out["fp32_vs_fp64"] = {
-            "speedup": value / v64, "fp64_value": v64, "steps_compared": Wm + K,
-            "l2_rel_diff": diff / float(torch.linalg.vector_norm(Q64)),
-            "l2_rel_diff_to_change": diff / float(torch.linalg.vector_norm(Q64 - Q0)),
-        }
-        del s64, Q64, r64
+    if not args.no_precision_clause:
+        out["fp32_mfma_vs_fp64"] = precision_clause(args, n, p, L, Q0, dt, K, Wm, graph, value)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, p, L, args.cpu_seconds)

@@ -25,8 +25,8 @@
  *     node (i,j,k) sits at the Gauss-Legendre points (xi_i, xi_j, xi_k) of
  *     that box.  Neighbours are periodic.
  *   Alignment.  State arrays must be 8-byte aligned, as any array of doubles
-     is (DG_EINVAL otherwise): the kernels read them in 8- and 16-byte pieces.
-   Ownership.  The caller owns every array and the workspace (allocated by
+ *     is (DG_EINVAL otherwise): the kernels read them in 8- and 16-byte pieces.
+ *   Ownership.  The caller owns every array and the workspace (allocated by
  *     PyTorch or hipMalloc); the library owns only the context.  The library
  *     performs no device allocation.
  *   Streams.  Every call runs asynchronously on the context's stream (default
@@ -201,22 +201,49 @@ int dg_rhs_vjp(dg_ctx* ctx, const double* Q, const double* gR, double* gQ);
  * layout above; gQ and gres must not overlap each other or Qs. */
 int dg_rk_stage_vjp(dg_ctx* ctx, int s, const double* Qs, double* gQ, double* gres, double dt);
 
+/* Gradient of the integrated kinetic energy (out[5] of dg_integrals) with
+ * respect to every nodal value of Q, written to gQ (overwritten):
+ * d/d rho = -|u|^2/2 Jw, d/d(rho u_d) = u_d Jw, d/d(rho E) = 0, with Jw the
+ * weight J w_i w_j w_k of the node in the collocated Gauss-Legendre rule of
+ * Section II-B.  Not in the paper: the adjoint of the objective that the
+ * differentiation extension uses (dg_rhs_vjp, dg_rk_stage_vjp).  Q (read) and
+ * gQ (written) are device arrays in the layout above; gQ must not overlap Q. */
+int dg_kinetic_energy_grad(dg_ctx* ctx, const double* Q, double* gQ);
+
 /* SYNCHRONISING.  Domain integrals by the nodal Gauss-Legendre rule:
  * out[0..4] = integral of the five conserved fields, out[5] = integral of
- * the kinetic energy |rho u|^2/(2 rho).  out is a HOST array of 6 doubles.
- * Summation order is fixed (bitwise reproducible). */
+ * the kinetic energy |rho u|^2/(2 rho).  The conserved integrals are the
+ * quantities whose rate of change Eq. (1) states in conservation form (zero
+ * on a periodic mesh, as the weak form of Eq. (5) keeps discretely); the
+ * rule is the collocated Gauss-Legendre quadrature of Section II-B, exact for
+ * the nodal polynomial.  out is a HOST array of 6 doubles.  Summation order
+ * is fixed (bitwise reproducible). */
 int dg_integrals(dg_ctx* ctx, const double* Q, double out[6]);
 
-/* SYNCHRONISING.  *out = max over nodes of sum_d (|u_d| + c)/h_d
- * (units 1/time; a CFL time step is CFL/((2p+1) * *out)).  out is HOST. */
+/* SYNCHRONISING.  *out = max over nodes of sum_d (|u_d| + c)/h_d, built
+ * from the wave speed |u_n| + c of the Lax-Friedrichs flux (Section II-B)
+ * with the sound speed c = sqrt(gamma p / rho) of the closure Eq. (3)
+ * (units 1/time; a CFL time step is CFL/((2p+1) * *out), a rule the paper
+ * does not state).  out is HOST. */
 int dg_max_wavespeed(dg_ctx* ctx, const double* Q, double* out);
 
 /* SYNCHRONISING.  DG_OK if every node has finite values, rho > 0 and
- * p > 0; DG_ENONPHYSICAL otherwise. */
+ * p > 0 (p from Eq. (3)); DG_ENONPHYSICAL otherwise.  The paper's scheme has
+ * no limiter, so the check is opt-in and never part of the hot path. */
 int dg_check_state(dg_ctx* ctx, const double* Q);
 
+/* Not in the paper: accuracy check of the reciprocal and square root that
+ * the flux kernels use (1/rho at every node and face point, the sound speed
+ * sqrt(gamma p / rho) of the Lax-Friedrichs wave speed, Section II-B).  For
+ * i < n: r[i] = 1/x[i], s[i] = sqrt(x[i]) computed exactly as inside the
+ * kernels.  x, r, s are DEVICE arrays of n doubles that must not overlap;
+ * the launch is enqueued on hip_stream (NULL = default stream). */
+int dg_recip_sqrt(const double* x, double* r, double* s, int64_t n, void* hip_stream);
+
 /* ---- batched independent meshes ---------------------------------------
- * Many independent periodic meshes of uneven size and degree advanced
+ * Not in the paper: an extension of its hot path to many small problems on
+ * one GPU (the per-mesh arithmetic is that of Section II-B and Sections
+ * IV-V, unchanged).  Many independent periodic meshes of uneven size and degree advanced
  * together: one persistent launch per RK stage walks a work list of
  * (mesh, element block) items, with a per-degree code path and per-degree
  * elements-per-workgroup tile (dg_batch_set_tile).  The arithmetic on every
@@ -260,7 +287,8 @@ int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps);
  * step parity; recaptured when the pointers change). */
 int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps);
 
-/* Opt-in per-launch timing for benchmarks.  While on, the context brackets
+/* Not in the paper: measurement support.  Opt-in per-launch timing for
+ * benchmarks.  While on, the context brackets
  * every kernel it launches with HIP events on its stream (a few microseconds
  * of overhead per launch).  Kinds: 0 face-trace kernel, 1 RK stage kernel of
  * stages 2..5, 2 RHS kernel, 3 adjoint kernels, 4 reductions, 5 RK stage

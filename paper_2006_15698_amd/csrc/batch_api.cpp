@@ -35,7 +35,7 @@ struct dg_batch {
   const double* gQ = nullptr;
   const double* gR = nullptr;
   int gprec = -1;
-  unsigned grid = 0;
+  unsigned grid[2] = {0, 0};   // persistent grid per precision (FP64, FP32 form)
 };
 
 namespace {
@@ -88,9 +88,9 @@ DGBatchLaunch launch_of(const dg_batch* b, hipStream_t s) {
   l.inst = (const DGBatchInst*)(b->ws + L.off_inst);
   l.items = (const int2*)(b->ws + L.off_items);
   l.nitems = (int)b->items.size();
-  l.grid = b->grid;
-  l.stream = s;
   l.f32 = b->precision == DG_FP32_MFMA;
+  l.grid = b->grid[l.f32];
+  l.stream = s;
   return l;
 }
 
@@ -180,12 +180,12 @@ dg_batch* dg_batch_create(int count, const int* n, const int* p, const double* L
   }
   b->qoff[count] = q;
   build_items(b);
+  // The persistent grid holds the workgroups that can be resident at once
+  // (compute units x workgroups per CU of that precision's kernel).
   int dev = 0, ncu = 0;
-  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) {
-    b->grid = (unsigned)(ncu * dg_batch_blocks_per_cu(0));
-  } else {
-    b->grid = 1024;
-  }
+  const bool have_cu = hipGetDevice(&dev) == hipSuccess &&
+                       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0;
+  for (int f32 = 0; f32 < 2; ++f32) b->grid[f32] = have_cu ? (unsigned)(ncu * dg_batch_blocks_per_cu(f32)) : 1024u;
   return b;
 }
 

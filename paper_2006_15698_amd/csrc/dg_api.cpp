@@ -325,6 +325,10 @@ DGWorkspace dg_workspace_layout(const dg_ctx* c) {
   return L;
 }
 
+// r = 1/x and s = sqrt(x) elementwise with the flux kernels' recip/root
+// (kern_check.hip).
+int dg_launch_recip_root(hipStream_t stream, const double* x, double* r, double* s, int64_t n);
+
 extern "C" {
 
 const char* dg_last_error(void) { return g_err; }
@@ -692,6 +696,28 @@ int dg_rk_stage_vjp(dg_ctx* c, int s, const double* Qs, double* gQ, double* gres
   if (err) return hip_fail(err, "vjp launch");
   err = timed(c, TK_VJP, [&] { return dg_launch_rk_reverse(c, n, v, dt, kRKA[s], gtot, gQ, gres); });
   if (err) return hip_fail(err, "reverse stage launch");
+  return DG_OK;
+}
+
+int dg_kinetic_energy_grad(dg_ctx* c, const double* Q, double* gQ) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  rc = check_state_pair(c, Q, "Q", gQ, "gQ");
+  if (rc) return rc;
+  int err = timed(c, TK_VJP, [&] { return dg_launch_ke_grad(c, Q, gQ); });
+  if (err) return hip_fail(err, "kinetic-energy gradient launch");
+  return DG_OK;
+}
+
+int dg_recip_sqrt(const double* x, double* r, double* s, int64_t n, void* stream) {
+  if (n < 0) return fail(DG_EINVAL, "n must be >= 0");
+  if (n == 0) return DG_OK;
+  if (!x || !r || !s) return fail(DG_EINVAL, "NULL array");
+  if (misaligned(x) || misaligned(r) || misaligned(s)) return fail(DG_EINVAL, "arrays must be 8-byte aligned");
+  const size_t b = (size_t)n * sizeof(double);
+  if (overlap(x, r, b) || overlap(x, s, b) || overlap(r, s, b)) return fail(DG_EALIAS, "arrays overlap");
+  int err = dg_launch_recip_root((hipStream_t)stream, x, r, s, n);
+  if (err) return hip_fail(err, "recip/sqrt launch");
   return DG_OK;
 }
 

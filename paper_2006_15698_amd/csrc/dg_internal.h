@@ -127,6 +127,9 @@ int dg_launch_reduce(const dg_ctx* c, const double* Q, double* red);
 // Adjoint RHS.
 int dg_launch_vjp(const dg_ctx* c, const double* Q, const double* gR, double* gQ, char* scratch);
 
+// Gradient of the kinetic-energy integral with respect to Q.
+int dg_launch_ke_grad(const dg_ctx* c, const double* Q, double* G);
+
 int dg_launch_axpy(const dg_ctx* c, int64_t n, const double* x, double b, const double* y, double* out);
 int dg_launch_rk_reverse(const dg_ctx* c, int64_t n, const double* v, double dt, double a, const double* gtot,
                          double* gQ, double* gres);

@@ -648,6 +648,37 @@ k_rk_reverse(int64_t n, const double* __restrict__ v, double dt, double a, const
   }
 }
 
+// Gradient of the kinetic-energy integral sum_e J sum_q w_q |m_q|^2 / (2 rho_q)
+// (the nodal Gauss-Legendre rule of the domain integrals) with respect to
+// every nodal value: d/d rho = -|u|^2/2 Jw, d/d m_d = u_d Jw, d/d (rho E) = 0,
+// with u = m / rho and Jw = J w_i w_j w_k of the node.
+template <int N>
+__global__ void __launch_bounds__(256)
+k_ke_grad(DGTables tb, const double* __restrict__ Q, double* __restrict__ G) {
+  constexpr int N3 = N * N * N;
+  const int64_t total = (int64_t)tb.E * N3;
+  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
+    const int t = (int)(g % N3);
+    const int i = t % N, j = (t / N) % N, k = t / (N * N);
+    const double jw = tb.J * tb.w[i] * tb.w[j] * tb.w[k];
+    const double rinv = 1.0 / Q[g];
+    const double u = Q[total + g] * rinv, v = Q[2 * total + g] * rinv, w = Q[3 * total + g] * rinv;
+    G[g] = -0.5 * (u * u + v * v + w * w) * jw;
+    G[total + g] = u * jw;
+    G[2 * total + g] = v * jw;
+    G[3 * total + g] = w * jw;
+    G[4 * total + g] = 0.0;
+  }
+}
+
+template <int N>
+int launch_ke_grad_n(const dg_ctx* c, const double* Q, double* G) {
+  const int64_t blocks64 = (c->E * N * N * N + 255) / 256;
+  const unsigned grid = (unsigned)(blocks64 < 65536 ? (blocks64 > 0 ? blocks64 : 1) : 65536);
+  hipLaunchKernelGGL(k_ke_grad<N>, dim3(grid), dim3(256), 0, c->stream, c->tab, Q, G);
+  return (int)hipGetLastError();
+}
+
 template <int N>
 int launch_vjp_n(const dg_ctx* c, const double* Q, const double* gR, double* gQ, double* TQ, double* TG) {
   constexpr int EPB = VCfg<N>::EPB;
@@ -712,4 +743,18 @@ int dg_launch_rk_reverse(const dg_ctx* c, int64_t n, const double* v, double dt,
   const unsigned grid = (unsigned)(blocks64 < 65536 ? (blocks64 > 0 ? blocks64 : 1) : 65536);
   hipLaunchKernelGGL(k_rk_reverse, dim3(grid), dim3(256), 0, c->stream, n, v, dt, a, gtot, gQ, gres);
   return (int)hipGetLastError();
+}
+
+int dg_launch_ke_grad(const dg_ctx* c, const double* Q, double* G) {
+  switch (c->N) {
+    case 1: return launch_ke_grad_n<1>(c, Q, G);
+    case 2: return launch_ke_grad_n<2>(c, Q, G);
+    case 3: return launch_ke_grad_n<3>(c, Q, G);
+    case 4: return launch_ke_grad_n<4>(c, Q, G);
+    case 5: return launch_ke_grad_n<5>(c, Q, G);
+    case 6: return launch_ke_grad_n<6>(c, Q, G);
+    case 7: return launch_ke_grad_n<7>(c, Q, G);
+    case 8: return launch_ke_grad_n<8>(c, Q, G);
+    default: return (int)hipErrorInvalidValue;
+  }
 }

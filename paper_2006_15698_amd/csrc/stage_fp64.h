@@ -56,10 +56,11 @@ __device__ __forceinline__ int neighbour(int nx, int ny, int nz, int e, int d, i
 // direction is a template parameter so that every array index is static
 // (a runtime index would force qm/qp into scratch memory).
 // 1/a: the hardware reciprocal estimate refined by two Newton-Raphson steps
-// r <- r + r (1 - a r) in FMA form, about half the instructions of a division.  On 2^26 log-uniform
-// inputs in [2^-12, 2^12] it equals the correctly rounded quotient bit for
-// bit.  A zero or non-finite input gives NaN or infinity, as the state is
-// then non-physical anyway.
+// r <- r + r (1 - a r) in FMA form, about half the instructions of a division.  On the 2^22 seeded
+// inputs of the library's accuracy check (dg_recip_sqrt: log-uniform in
+// [2^-12, 2^12], near 1, powers of two, 60..120) it equals the correctly
+// rounded quotient bit for bit.  A zero or non-finite input gives NaN or
+// infinity, as the state is then non-physical anyway.
 __device__ __forceinline__ double recip(double a) {
   double r = __builtin_amdgcn_rcp(a);
   double e = fma(-a, r, 1.0);
@@ -72,7 +73,7 @@ __device__ __forceinline__ double recip(double a) {
 // coupled Newton step on g = x y ~ sqrt(x) and h = y/2 ~ 1/(2 sqrt(x)) (the
 // FMA square-root iteration described by Markstein for IA-64), then a final
 // correction of g with the residual x - g^2 (0 for x = 0).  Equal to
-// the correctly rounded square root bit for bit on the same test inputs.
+// the correctly rounded square root bit for bit on the same checked inputs.
 __device__ __forceinline__ double root(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;

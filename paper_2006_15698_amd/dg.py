@@ -73,6 +73,8 @@ _SIGS = {
     "dg_rk_graph_steps": (_i, [_vp, _vp, _vp, _d, _i]),
     "dg_rhs_vjp": (_i, [_vp, _vp, _vp, _vp]),
     "dg_rk_stage_vjp": (_i, [_vp, _i, _vp, _vp, _vp, _d]),
+    "dg_kinetic_energy_grad": (_i, [_vp, _vp, _vp]),
+    "dg_recip_sqrt": (_i, [_vp, _vp, _vp, _i64, _vp]),
     "dg_integrals": (_i, [_vp, _vp, _dp]),
     "dg_max_wavespeed": (_i, [_vp, _vp, _dp]),
     "dg_check_state": (_i, [_vp, _vp]),
@@ -240,6 +242,18 @@ def dg_rhs_vjp(ctx, Q, gR, gQ):
 def dg_rk_stage_vjp(ctx, s, Qs, gQ, gres, dt):
     nd = _nd(ctx)
     return _check(_lib.dg_rk_stage_vjp(ctx, int(s), _ptr(Qs, nd), _ptr(gQ, nd), _ptr(gres, nd), float(dt)))
+
+
+def dg_kinetic_energy_grad(ctx, Q, gQ):
+    nd = _nd(ctx)
+    return _check(_lib.dg_kinetic_energy_grad(ctx, _ptr(Q, nd), _ptr(gQ, nd)))
+
+
+def dg_recip_sqrt(x, r, s, stream=None):
+    """r = 1/x, s = sqrt(x) elementwise with the kernels' own reciprocal and
+    square root (float64 device tensors of equal size)."""
+    n = x.numel()
+    return _check(_lib.dg_recip_sqrt(_ptr(x, n), _ptr(r, n), _ptr(s, n), n, _stream_ptr(stream)))
 
 
 def dg_integrals(ctx, Q):
@@ -571,26 +585,13 @@ def rk_gradient(solver, Q0, dt, nsteps, objective_grad, every=8):
     return gQ, Qfinal
 
 
-def kinetic_energy_weights(solver):
-    """J w_i w_j w_k per node, shaped like one field of the state (for
-    objectives built from the kinetic energy |rho u|^2 / (2 rho))."""
-    xi, w = dg_quadrature(solver.p)
-    nx, ny, nz = solver.n
-    hx, hy, hz = (solver.L[0] / nx, solver.L[1] / ny, solver.L[2] / nz)
-    w3 = np.einsum("k,j,i->kji", w, w, w) * (hx * hy * hz / 8.0)
-    wt = torch.from_numpy(np.ascontiguousarray(w3)).to(solver.device)
-    return wt.reshape(1, 1, 1, solver.N, solver.N, solver.N).expand(nz, ny, nx, -1, -1, -1)
-
-
 def kinetic_energy_grad(solver):
-    """d/dQ of the integrated kinetic energy sum J w |rho u|^2 / (2 rho)."""
-    wt = kinetic_energy_weights(solver)
+    """d/dQ of the integrated kinetic energy (dg_integrals' last value),
+    computed by the library (dg_kinetic_energy_grad), as a function of Q."""
 
     def grad(Q):
-        rho, m = Q[0], Q[1:4]
-        u = m / rho
-        g = torch.zeros_like(Q)
-        g[0] = -0.5 * (u * u).sum(0) * wt
-        g[1:4] = u * wt
+        g = torch.empty_like(Q)
+        solver._s()
+        dg_kinetic_energy_grad(solver.ctx, Q, g)
         return g
     return grad

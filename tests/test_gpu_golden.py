@@ -61,8 +61,11 @@ def test_tgv48_p4_fp64_50_steps(golden):
     samp, I, samp0 = _run(golden, dg.DG_FP64)
     rel_state, rel_change, l2_change = _errors(golden, samp, samp0)
     print("state-relative", rel_state, "change-relative", rel_change, "L2 relative to change", l2_change)
-    assert np.all(rel_state <= 1e-12)
-    assert np.all(rel_change <= 1e-8)
+    # measured on MI355X: state-relative <= 1.4e-14, L2 <= 2.8e-10 of the
+    # 50-step change per field; bars about 3-4x those (250 stages of state
+    # rounding on either side, in the same order each time)
+    assert np.all(rel_state <= 5e-14)
+    assert np.all(l2_change <= 1e-9)
     I0, Io = golden["integrals0"], golden["integrals"]
     # conserved integrals: both runs conserve to roundoff of the sums
     scale = np.array([I0[0], I0[0], I0[0], I0[0], I0[4]])
@@ -83,5 +86,7 @@ def test_tgv48_p4_fp32_form_50_steps(golden):
     rel_state, rel_change, l2_change = _errors(golden, samp, samp0)
     print("fp32 form: state-relative", rel_state, "change-relative", rel_change,
           "L2 relative to change", l2_change)
-    assert np.all(rel_state <= 1e-7)
-    assert np.all(l2_change <= 1e-3)
+    # stated bound, not a parity claim: measured state-relative 6.8e-9 and
+    # L2 2.0e-5 of the 50-step change (worst field); bars about 3x those
+    assert np.all(rel_state <= 2e-8)
+    assert np.all(l2_change <= 6e-5)

@@ -139,13 +139,21 @@ def test_tgv_c2_steps_vs_oracle(dgm):
     Qh = _host(Qg)
     # state-relative bar (the state is O(p0) for energy)
     assert _rel(Qh, Qo) <= TOL
-    # change-relative: the update itself matches
+    # Rounding bar: each of the 15 stages rounds the updated state once on
+    # either side (Q + b res), so the two runs may drift apart by about
+    # 2 x 15 ulp of the state; the right-hand sides agree to 1e-12 of their
+    # size, and dt times that is far below an ulp of Q here.  Bar: 4x that
+    # drift, per field against the field's scale (momentum components against
+    # the momentum vector's size: w = 0 in the TGV).  In units of the 3-step
+    # change (~3e-6 of the density) this is ~1e-9, so the update itself is
+    # checked to that fraction.
     dq = np.abs(Qh - Qo).reshape(5, -1).max(axis=1)
+    m = np.abs(Qo).reshape(5, -1).max(axis=1)
+    scale = np.array([m[0], m[1:4].max(), m[1:4].max(), m[1:4].max(), m[4]])
     ch = np.abs(Qo - Q0).reshape(5, -1).max(axis=1)
-    print("change-relative", dq / ch)
-    # after 3 steps the density changes by ~3e-6 of itself, so FP64 rounding
-    # of the state alone is ~1e-10 of the change
-    assert np.all(dq <= 1e-8 * ch)
+    bar = 4 * 2 * 15 * np.finfo(float).eps * scale
+    print("state error / rounding bar", dq / bar, "change-relative", dq / ch)
+    assert np.all(dq <= bar)
 
 
 def test_integrals_and_wavespeed(dgm):

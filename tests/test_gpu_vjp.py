@@ -166,6 +166,26 @@ def test_c5_gradient_vs_central_differences_64_directions(dgm):
     print("worst |fd - adjoint|", worst)
 
 
+@pytest.mark.parametrize("p", [1, 3, 4])
+def test_kinetic_energy_grad_vs_oracle_complex_step(dgm, p):
+    """dg_kinetic_energy_grad dotted with seeded directions equals the
+    complex-step derivative of the oracle's kinetic-energy integral; the
+    energy field has zero gradient."""
+    n, L = (3, 4, 2), (1.0, 0.7, 1.2)
+    Q = W.random_smooth(n, p, seed=80 + p, L=L, noise=0.05)
+    ora = DG(n, p, L=L)
+    s = dgm.Solver(n, p, L=L)
+    G = _host(dgm.kinetic_energy_grad(s)(_dev(Q)))
+    assert np.all(G[4] == 0.0)
+    rng = np.random.default_rng(90 + p)
+    h = 1e-30
+    for _ in range(4):
+        V = rng.standard_normal(Q.shape)
+        ref = ora.integrals(Q + 1j * h * V)[5].imag / h
+        got = float(np.dot(G.ravel(), V.ravel()))
+        assert abs(got - ref) <= 1e-13 * np.linalg.norm(G) * np.linalg.norm(V), (got, ref)
+
+
 def test_checkpointing_interval_does_not_change_gradient(dgm):
     import torch
     n, p = (4, 4, 4), 2
