@@ -28,6 +28,10 @@ Parity status per function (each pin lives in ``tests/test_oracle_*.py``):
                                  temporal convergence rate)
   adjoint.*                      pinned (complex-step vs central differences,
                                  dot-product identity)
+  viscous.NavierStokesDG         pinned (mu = 0 is Euler, free stream,
+                                 conservation, gradient convergence, symmetric
+                                 negative heat-conduction operator, shear-wave
+                                 rate convergence, independent 1-D BR1 code)
 """
 
-from . import quadrature, euler, dg, lserk  # noqa: F401
+from . import quadrature, euler, dg, lserk, viscous  # noqa: F401

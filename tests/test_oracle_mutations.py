@@ -18,7 +18,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["test_oracle_quadrature.py", "test_oracle_euler.py", "test_oracle_dg.py", "test_oracle_lserk.py",
-             "test_oracle_adjoint.py"]
+             "test_oracle_adjoint.py", "test_oracle_viscous.py"]
 
 # (oracle file, exact text, replacement, what the mistake is)
 MUTATIONS = [
@@ -47,6 +47,18 @@ MUTATIONS = [
      "one Runge-Kutta coefficient off in the last digit"),
     ("quadrature.py", "weights = 2.0 * vecs[0, :] ** 2", "weights = 2.0 * vecs[0, :] ** 2 * (1 + 1e-9)",
      "quadrature weights off by 1e-9"),
+    ("viscous.py", "tau = tau - (2.0 / 3.0) * self.mu * div", "tau = tau - (1.0 / 3.0) * self.mu * div",
+     "wrong bulk-viscosity factor"),
+    ("viscous.py", "tau = self.mu * (grad_u[d, k] + grad_u[k, d])", "tau = self.mu * (grad_u[d, k] + grad_u[d, k])",
+     "velocity gradient not symmetrised"),
+    ("viscous.py", "mean = 0.5 * (own + nbr)", "mean = own", "one-sided instead of central face value"),
+    ("viscous.py", "nbr = (np.roll(X, -1, axis=ax)", "nbr = (np.roll(X, 1, axis=ax)", "wrong neighbour in the lifting"),
+    ("viscous.py", "en = self.kappa * theta[d, 3]", "en = 0.0 * theta[d, 3]", "heat flux dropped"),
+    ("viscous.py", "/ (self.gamma - 1.0)) / self.prandtl", "/ (self.gamma - 1.0)) * self.prandtl",
+     "conductivity multiplied by the Prandtl number"),
+    ("viscous.py", "out = np.linalg.solve(self.M, (S - V)", "out = np.linalg.solve(self.M, (V - S)",
+     "sign of the weak derivative"),
+    ("viscous.py", "en = en + vel[k] * tau", "en = en", "viscous work dropped from the energy flux"),
 ]
 
 

@@ -1,0 +1,216 @@
+"""Pins of the viscous (Navier-Stokes, BR1) oracle, ``oracle/viscous.py``.
+
+What the mathematics fixes, independently of the oracle's own code:
+  - mu = 0 gives the Euler right-hand side exactly;
+  - a uniform state has zero gradients and zero viscous right-hand side;
+  - central viscous face fluxes telescope: the discrete integrals of mass,
+    momentum and energy do not change (periodic mesh);
+  - the BR1 gradient of smooth periodic fields converges to the exact
+    gradient as the mesh is refined;
+  - heat conduction alone (u = 0, uniform density) is the BR1 Laplacian of
+    the temperature times kappa, which is symmetric and negative
+    semi-definite in the mass-matrix inner product (the central-flux
+    divergence is minus the adjoint of the central-flux gradient);
+  - a shear wave v = eps sin(2 pi x), u = w = 0, uniform rho and p has the
+    exact y-momentum rate mu v_xx and zero x-momentum and mass rates, and the
+    discrete rate converges to it;
+  - for fields that vary along x only with velocity along x, the viscous
+    right-hand side equals that of an independent brute-force 1-D BR1 code
+    (scalar loops, numpy's Gauss-Legendre rule, barycentric derivatives,
+    its own 4/3 mu normal stress).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.dg import DG
+from oracle.viscous import NavierStokesDG
+
+GAMMA = 1.4
+
+
+def test_zero_viscosity_is_euler():
+    n, p, L = (3, 2, 4), 2, (1.0, 0.8, 1.3)
+    Q = W.random_smooth(n, p, seed=3, L=L, noise=0.05)
+    assert np.array_equal(NavierStokesDG(n, p, L=L, mu=0.0).rhs(Q), DG(n, p, L=L).rhs(Q))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_uniform_state_has_no_viscous_rate(p):
+    n, L = (3, 2, 2), (1.0, 0.7, 1.1)
+    Q = W.uniform_state(n, p, 1.3, (0.4, -0.2, 0.7), 2.1)
+    ns = NavierStokesDG(n, p, L=L, mu=0.05)
+    th = ns.gradients(Q)
+    assert np.max(np.abs(th)) <= 1e-13
+    assert np.max(np.abs(ns.rhs_viscous(Q))) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_viscous_terms_conserve(p):
+    n, L = (3, 4, 2), (1.0, 0.9, 1.2)
+    Q = W.random_smooth(n, p, seed=20 + p, L=L, noise=0.05)
+    ns = NavierStokesDG(n, p, L=L, mu=0.03, prandtl=0.7)
+    R = ns.rhs_viscous(Q).reshape(5, -1, ns.N3)
+    w = ns.J * ns.wq
+    total = np.einsum("fet,t->f", R, w)
+    scale = np.einsum("fet,t->f", np.abs(R), w)
+    assert np.all(np.abs(total[1:]) <= 1e-13 * scale[1:])
+    assert np.max(np.abs(R[0])) == 0.0          # no viscous mass flux at all
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_gradient_converges_to_exact(p):
+    """theta of u = sin(2 pi x) cos(2 pi y), T = 1 + 0.3 cos(2 pi z) sin(2 pi x)
+    against the exact gradient (max norm): the observed order approaches p
+    (p+1 at even p) under refinement; the last rate is at least p - 0.15 and
+    every rate at least p - 0.5."""
+    errs = []
+    sizes = [8, 16, 32] if p == 1 else [4, 8, 16]
+    for m in sizes:
+        n = (m, m, m)
+        X, Y, Z = W.node_coords(n, p, (1.0, 1.0, 1.0))
+        tp = 2 * math.pi
+        u = np.sin(tp * X) * np.cos(tp * Y)
+        T = 1.0 + 0.3 * np.cos(tp * Z) * np.sin(tp * X)
+        rho = 1.0 + 0.0 * X
+        Q = W.conserved(rho, u, 0.0 * X, 0.0 * X, rho * T)
+        ns = NavierStokesDG(n, p, mu=0.01)
+        th = ns.gradients(Q).reshape(3, 4, m, m, m, -1)
+        sh = th.shape[2:]
+        exact_u = [tp * np.cos(tp * X) * np.cos(tp * Y), -tp * np.sin(tp * X) * np.sin(tp * Y), 0.0 * X]
+        exact_T = [0.3 * tp * np.cos(tp * Z) * np.cos(tp * X), 0.0 * X, -0.3 * tp * np.sin(tp * Z) * np.sin(tp * X)]
+        e = 0.0
+        for d in range(3):
+            e = max(e, np.max(np.abs(th[d, 0] - exact_u[d].reshape(sh))))
+            e = max(e, np.max(np.abs(th[d, 3] - exact_T[d].reshape(sh))))
+        errs.append(e)
+    rates = [math.log(errs[i] / errs[i + 1], 2) for i in range(len(errs) - 1)]
+    assert rates[-1] >= p - 0.15 and min(rates) >= p - 0.5, (errs, rates)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_heat_conduction_is_symmetric_negative_laplacian(p):
+    """u = 0, rho = 1: the energy rate is kappa L T, L the BR1 Laplacian.
+    <T1, L T2>_M = <L T1, T2>_M, <T, L T>_M <= 0, L 1 = 0."""
+    n, L = (3, 2, 2), (1.0, 0.8, 1.2)
+    ns = NavierStokesDG(n, p, L=L, mu=0.2, prandtl=0.8)
+    rng = np.random.default_rng(p)
+    shape = (n[2], n[1], n[0], p + 1, p + 1, p + 1)
+    zero = np.zeros(shape)
+    one = np.ones(shape)
+    w = np.broadcast_to(ns.J * ns.wq, (int(np.prod(n)), ns.N3)).reshape(shape)
+
+    def lap(T):
+        Q = W.conserved(one, zero, zero, zero, one * T)     # p = rho T with rho = 1
+        return ns.rhs_viscous(Q)[4] / ns.kappa
+
+    T1 = 1.0 + 0.1 * rng.standard_normal(shape)
+    T2 = 1.0 + 0.1 * rng.standard_normal(shape)
+    a = np.sum(w * T1 * lap(T2))
+    b = np.sum(w * lap(T1) * T2)
+    scale = np.sum(w * np.abs(T1 * lap(T2)))
+    assert abs(a - b) <= 1e-12 * scale
+    for T in (T1, T2, T1 - T2):
+        assert np.sum(w * T * lap(T)) <= 1e-12 * scale
+    assert np.max(np.abs(lap(3.0 * one))) <= 1e-10
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_shear_wave_rate(p):
+    """v = eps sin(2 pi x): the viscous part of d(rho v)/dt converges to
+    mu v_xx = -mu (2 pi)^2 v; its x-momentum and mass parts vanish to
+    rounding (tau_xx = 0 as div u = 0, tau_xy depends on x only).  The BR1
+    second derivative converges in the max norm at the nodes like h^p at even
+    p and h^(p-1) at odd p except p = 1, which converges like h (measured
+    0.94, 2.0 and 2.1 at p = 1, 2, 3 over 16 -> 32 elements); the pin asks
+    the finest rate to be within 0.15 of that order."""
+    mu, eps, tp = 0.05, 1e-3, 2 * math.pi
+    errs = []
+    for m in (8, 16, 32):
+        n = (m, 2, 2)
+        X, Y, Z = W.node_coords(n, p, (1.0, 1.0, 1.0))
+        v = eps * np.sin(tp * X)
+        one = np.ones(X.shape)
+        Q = W.conserved(one, 0.0 * one, v, 0.0 * one, one)
+        ns = NavierStokesDG(n, p, mu=mu)
+        R = ns.rhs_viscous(Q)
+        exact = -mu * tp * tp * v
+        errs.append(np.max(np.abs(R[2] - exact)) / np.max(np.abs(exact)))
+        assert np.max(np.abs(R[1])) <= 1e-12 * np.max(np.abs(exact))
+        assert np.max(np.abs(R[0])) <= 1e-12 * np.max(np.abs(exact))
+    rates = [math.log(errs[i] / errs[i + 1], 2) for i in range(2)]
+    expected = {1: 1.0, 2: 2.0, 3: 2.0}[p]
+    assert rates[-1] >= expected - 0.15, (errs, rates)
+    assert errs[-1] <= {1: 0.12, 2: 0.005, 3: 0.002}[p], errs
+
+
+# --------------------------------------------------------------------------
+# an independent brute-force 1-D BR1 code (scalar loops)
+def _brute_1d_viscous(rho, mom, en, h, N, mu, prandtl):
+    """Viscous right-hand side of 1-D Navier-Stokes (rho, rho u, rho E) on a
+    periodic line of n elements with N Gauss-Legendre nodes each:
+    u = m/rho, T = p/rho; BR1 gradients with central face means; flux
+    (0, 4/3 mu u_x, 4/3 mu u u_x + kappa T_x); BR1 derivative of the flux."""
+    xi, w = np.polynomial.legendre.leggauss(N)
+    bw = [1.0 / np.prod([xi[i] - xi[m] for m in range(N) if m != i]) for i in range(N)]
+    D = [[0.0] * N for _ in range(N)]          # D[a][i] = l_i'(xi_a)
+    for a in range(N):
+        for i in range(N):
+            if a != i:
+                D[a][i] = (bw[i] / bw[a]) / (xi[a] - xi[i])
+        D[a][a] = -sum(D[a][i] for i in range(N) if i != a)
+
+    def lag(x):
+        return [np.prod([(x - xi[m]) / (xi[i] - xi[m]) for m in range(N) if m != i]) for i in range(N)]
+    lp, lm = lag(1.0), lag(-1.0)
+    n = len(rho)
+    kappa = mu * (GAMMA / (GAMMA - 1.0)) / prandtl
+
+    def deriv(f):
+        """BR1 weak derivative of the nodal field f[e][i] with central face
+        means: (2/h)/w_i [-sum_a w_a D[a][i] f_a + l_i(1) {f}_R - l_i(-1) {f}_L]."""
+        tr_r = [sum(lp[a] * f[e][a] for a in range(N)) for e in range(n)]
+        tr_l = [sum(lm[a] * f[e][a] for a in range(N)) for e in range(n)]
+        out = [[0.0] * N for _ in range(n)]
+        for e in range(n):
+            right = 0.5 * (tr_r[e] + tr_l[(e + 1) % n])
+            left = 0.5 * (tr_r[(e - 1) % n] + tr_l[e])
+            for i in range(N):
+                vol = sum(w[a] * D[a][i] * f[e][a] for a in range(N))
+                out[e][i] = (2.0 / h) / w[i] * (-vol + lp[i] * right - lm[i] * left)
+        return out
+    u = [[mom[e][i] / rho[e][i] for i in range(N)] for e in range(n)]
+    T = [[(GAMMA - 1.0) * (en[e][i] - 0.5 * mom[e][i] ** 2 / rho[e][i]) / rho[e][i] for i in range(N)]
+         for e in range(n)]
+    ux, Tx = deriv(u), deriv(T)
+    fm = [[4.0 / 3.0 * mu * ux[e][i] for i in range(N)] for e in range(n)]
+    fe = [[u[e][i] * fm[e][i] + kappa * Tx[e][i] for i in range(N)] for e in range(n)]
+    return deriv(fm), deriv(fe)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_one_dimensional_reduction(p):
+    m, mu, pr = 5, 0.07, 0.72
+    n = (m, 2, 3)
+    X, _, _ = W.node_coords(n, p, (1.0, 1.0, 1.0))
+    tp = 2 * math.pi
+    rho = 1.0 + 0.2 * np.sin(tp * X + 0.3)
+    u = 0.4 * np.cos(tp * X) + 0.1
+    pres = 1.0 + 0.3 * np.sin(2 * tp * X)
+    z = 0.0 * X
+    Q = W.conserved(rho, u, z, z, pres)
+    ns = NavierStokesDG(n, p, mu=mu, prandtl=pr)
+    R = ns.rhs_viscous(Q)
+    N = p + 1
+    # one x-line of elements (ey = ez = 0, j = k = 0): Q[f, 0, 0, e, 0, 0, i]
+    line = Q[:, 0, 0, :, 0, 0, :]
+    rm, re = _brute_1d_viscous(line[0].tolist(), line[1].tolist(), line[4].tolist(), 1.0 / m, N, mu, pr)
+    scale = np.max(np.abs(R))
+    assert np.max(np.abs(R[1, 0, 0, :, 0, 0, :] - np.array(rm))) <= 1e-12 * scale
+    assert np.max(np.abs(R[4, 0, 0, :, 0, 0, :] - np.array(re))) <= 1e-12 * scale
+    # every other line is the same, and there is no y/z momentum rate
+    assert np.max(np.abs(R - R[:, :1, :1, :, :1, :1, :])) <= 1e-12 * scale
+    assert np.max(np.abs(R[2:4])) <= 1e-12 * scale
