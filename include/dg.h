@@ -176,6 +176,22 @@ int dg_rk_step(dg_ctx* ctx, double* Q, double* res, double dt);
  * dg_rk_step. */
 int dg_rk_steps(dg_ctx* ctx, double* Q, double* res, double dt, int nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * nsteps LSERK45 steps as dg_rk_steps, bitwise the same result, with the
+ * second state buffer of the neighbour-read ping-pong taken from a
+ * library-held static device buffer of DG_NOALLOC_MAX_BYTES (128 MiB, one
+ * per GPU, held until the process ends) instead of the workspace.  Needs no
+ * workspace (none need be set) and calls no allocating routine; the stages
+ * always use the neighbour-read exchange (bitwise equal to the trace-buffer
+ * one) and are never timed by dg_set_timing.  DG_EUNSUPPORTED if the state
+ * (5 E N^3 doubles) exceeds DG_NOALLOC_MAX_BYTES.  Every call on one GPU
+ * shares that buffer: calls that overlap on one GPU (other streams, other
+ * threads, other contexts) race and must be serialised by the caller.  The
+ * buffer holds nothing between calls that a later call relies on. */
+#define DG_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+int dg_rk_steps_noalloc(dg_ctx* ctx, double* Q, double* res, double dt, int nsteps);
+
 /* As dg_rk_steps (bitwise the same result), with each step's five stage
  * launches captured once in a HIP graph (one per ping-pong parity of the
  * neighbour-read exchange) and replayed nsteps times on an internal stream

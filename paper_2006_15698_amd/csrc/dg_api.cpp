@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -183,16 +184,21 @@ double* q2_buf(dg_ctx* c) { return (double*)(c->ws + dg_workspace_layout(c).off_
 
 // Neighbour-read sequencing: stage g reads buf[g % 2] and writes
 // buf[(g + 1) % 2] with buf = {Q, Q2}; an odd count ends in Q2, copied back.
-int stages_nb(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
-  double* buf[2] = {Q, q2_buf(c)};
+// Q2 is the workspace's second state buffer unless the caller names another
+// one; with `timing` false no launch is bracketed by timing events (which are
+// created on first use).
+int stages_nb(dg_ctx* c, double* Q, double* res, double dt, int s0, int count, double* q2 = nullptr,
+              bool timing = true) {
+  double* buf[2] = {Q, q2 ? q2 : q2_buf(c)};
   int err = 0;
   for (int g = 0; g < count; ++g) {
     const int s = (s0 + g) % 5;
-    err = timed(c, s == 0 ? TK_STAGE_FIRST : TK_STAGE, [&] {
+    auto launch = [&] {
       return c->precision == DG_FP32_MFMA
                  ? dg_launch_stage_nb_f32(c, buf[g & 1], buf[(g + 1) & 1], res, 1, kRKA[s], kRKB[s], dt, s == 0)
                  : dg_launch_stage_nb(c, buf[g & 1], buf[(g + 1) & 1], res, 1, kRKA[s], kRKB[s], dt, s == 0);
-    });
+    };
+    err = timing ? timed(c, s == 0 ? TK_STAGE_FIRST : TK_STAGE, launch) : launch();
     if (err) return hip_fail(err, "stage launch");
   }
   if (count & 1) {
@@ -221,6 +227,36 @@ int stages(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
     });
     if (err) return hip_fail(err, "stage launch");
   }
+  return DG_OK;
+}
+
+// Second state buffer for dg_rk_steps_noalloc: a file-scope device array,
+// one copy on every GPU the library runs on, kept until the process ends.  In
+// host code `scratch` names a host-side stand-in, not the device memory: the
+// device address is looked up once per device with hipGetSymbolAddress (while
+// that device is current) and only that address is ever handed to kernels
+// and copies.
+constexpr size_t kScratchBytes = DG_NOALLOC_MAX_BYTES;
+__device__ __align__(256) static double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_of_current_device(double** out) {
+  int dev = 0;
+  int err = (int)hipGetDevice(&dev);
+  if (err) return hip_fail(err, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DG_EUNSUPPORTED, "device ordinal %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    err = (int)hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err) return hip_fail(err, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(DG_EHIP, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch_dev[dev] = (double*)p;
+  }
+  *out = g_scratch_dev[dev];
   return DG_OK;
 }
 
@@ -587,6 +623,23 @@ int dg_rk_steps(dg_ctx* c, double* Q, double* res, double dt, int nsteps) {
 }
 
 int dg_rk_step(dg_ctx* c, double* Q, double* res, double dt) { return dg_rk_steps(c, Q, res, dt, 1); }
+
+int dg_rk_steps_noalloc(dg_ctx* c, double* Q, double* res, double dt, int nsteps) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  int rc = check_state_pair(c, Q, "Q", res, "res");
+  if (rc) return rc;
+  if (state_bytes(c) > kScratchBytes)
+    return fail(DG_EUNSUPPORTED, "state of %zu bytes exceeds the %zu-byte static buffer of dg_rk_steps_noalloc",
+                state_bytes(c), kScratchBytes);
+  if (nsteps == 0) return DG_OK;
+  if ((int64_t)nsteps * 5 > 0x7fffffffLL) return fail(DG_EINVAL, "too many steps");
+  double* q2 = nullptr;
+  rc = scratch_of_current_device(&q2);
+  if (rc) return rc;
+  return stages_nb(c, Q, res, dt, 0, 5 * nsteps, q2, false);
+}
 
 int dg_rk_graph_steps(dg_ctx* c, double* Q, double* res, double dt, int nsteps) {
   int rc = check_ready(c);

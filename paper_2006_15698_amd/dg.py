@@ -71,6 +71,7 @@ _SIGS = {
     "dg_rk_step": (_i, [_vp, _vp, _vp, _d]),
     "dg_rk_steps": (_i, [_vp, _vp, _vp, _d, _i]),
     "dg_rk_graph_steps": (_i, [_vp, _vp, _vp, _d, _i]),
+    "dg_rk_steps_noalloc": (_i, [_vp, _vp, _vp, _d, _i]),
     "dg_rhs_vjp": (_i, [_vp, _vp, _vp, _vp]),
     "dg_rk_stage_vjp": (_i, [_vp, _i, _vp, _vp, _vp, _d]),
     "dg_kinetic_energy_grad": (_i, [_vp, _vp, _vp]),
@@ -227,6 +228,14 @@ def dg_rk_step(ctx, Q, res, dt):
 def dg_rk_steps(ctx, Q, res, dt, nsteps):
     nd = _nd(ctx)
     return _check(_lib.dg_rk_steps(ctx, _ptr(Q, nd), _ptr(res, nd), float(dt), int(nsteps)))
+
+
+def dg_rk_steps_noalloc(ctx, Q, res, dt, nsteps):
+    nd = _nd(ctx)
+    return _check(_lib.dg_rk_steps_noalloc(ctx, _ptr(Q, nd), _ptr(res, nd), float(dt), int(nsteps)))
+
+
+DG_NOALLOC_MAX_BYTES = 128 << 20
 
 
 def dg_rk_graph_steps(ctx, Q, res, dt, nsteps):
