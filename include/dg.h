@@ -93,6 +93,23 @@ int dg_set_stream(dg_ctx* ctx, void* hip_stream);
  * DG_EUNSUPPORTED if the mode is not available for this p. */
 int dg_set_precision(dg_ctx* ctx, int mode);
 
+/* Viscous terms (Navier-Stokes).  The paper's CPU code has a viscous
+ * formulation (Section III, Fig. 2) that the paper does not print; the one
+ * built here: constant dynamic viscosity mu >= 0, Stokes' hypothesis,
+ * Fourier conduction with conductivity mu gamma / ((gamma - 1) Pr) (gas
+ * constant 1: T = p / rho), discretised by Bassi & Rebay's first scheme on
+ * the same collocated basis: the gradients of (u, v, w, T) are weak
+ * derivatives of their nodal interpolants with central face means, the
+ * viscous flux is evaluated at the nodes and enters Eq. (5) beside the
+ * inviscid flux with the central mean of both sides' traces.  mu = 0
+ * (default) is the Euler equations.  With mu > 0: dg_rhs, dg_rk_stage,
+ * dg_rk_step(s) and dg_rk_graph_steps (which then launches directly) add
+ * the viscous terms in FP64 (the inviscid part follows dg_set_precision);
+ * dg_workspace_bytes grows by 17 N^3 E doubles, so set the viscosity before
+ * the workspace; the adjoint calls and dg_rk_steps_noalloc return
+ * DG_EUNSUPPORTED.  DG_EINVAL for mu < 0, Pr <= 0 or non-finite values. */
+int dg_set_viscosity(dg_ctx* ctx, double mu, double prandtl);
+
 /* Tuning options (dg_set_option).
  * DG_OPT_EXCHANGE: how an FP64 stage obtains its neighbours' face traces.
  *   DG_EXCHANGE_NEIGHBOUR (default): interpolated in the launch itself from
@@ -281,6 +298,20 @@ int dg_batch_set_precision(dg_batch* b, int mode);
  * dg_batch_tile_options); changes the work list, so call it before
  * dg_batch_set_workspace. */
 int dg_batch_set_tile(dg_batch* b, int p, int epb);
+/* Order in which the persistent launch walks the work list; the results are
+ * bitwise the same for every setting.  Keys as for dg_set_option:
+ * DG_OPT_XCD_REMAP 1 cuts the work list into 8 contiguous parts of about
+ *   equal node count, one per XCD of the MI355X, so that the items that run
+ *   at the same time on one XCD are neighbours in the list and share its
+ *   L2; 0 (default) deals every item to the whole grid round robin.
+ * DG_OPT_ORDER: items of a mesh row by row (DG_ORDER_LINEAR, default) or in
+ *   pencils of DG_OPT_PENCIL_X elements (0 = the whole row) by
+ *   DG_OPT_PENCIL_Z planes swept along y (DG_ORDER_PENCIL; 16 x 8 when
+ *   chosen), which lists an item's y- and z-neighbours close to it.
+ * The work list is rebuilt (and re-uploaded, SYNCHRONISING, when a
+ * workspace is set); DG_EINVAL for an unknown key or a value out of range. */
+int dg_batch_set_option(dg_batch* b, int key, int value);
+int dg_batch_get_option(const dg_batch* b, int key, int* value);
 /* Up to max tile sizes available for degree p into out[]; returns count. */
 int dg_batch_tile_options(int p, int* out, int max);
 /* Doubles before mesh i's block (i = count gives the total length). */
@@ -307,15 +338,17 @@ int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps);
  * benchmarks.  While on, the context brackets
  * every kernel it launches with HIP events on its stream (a few microseconds
  * of overhead per launch).  Kinds: 0 face-trace kernel, 1 RK stage kernel of
- * stages 2..5, 2 RHS kernel, 3 adjoint kernels, 4 reductions, 5 RK stage
- * kernel of the first stage (whose coefficient a is zero, so it writes the
- * residual without reading it).  Switching on clears the record; at most
- * 65536 launches are recorded. */
+ * stages 2..5, 2 RHS kernel (also the inviscid rate of a viscous stage),
+ * 3 adjoint kernels, 4 reductions, 5 RK stage kernel of the first stage
+ * (whose coefficient a is zero, so it writes the residual without reading
+ * it), 6 the two viscous kernels of a right-hand side or stage (timed
+ * together).  Switching on clears the record; at most 65536 launches are
+ * recorded. */
 int dg_set_timing(dg_ctx* ctx, int on);
 
 /* SYNCHRONISING.  Summed milliseconds ms[k] and launch counts count[k] for
- * the six kinds above since timing was switched on.  HOST arrays of 6. */
-int dg_timing_read(dg_ctx* ctx, double ms[6], int64_t count[6]);
+ * the seven kinds above since timing was switched on.  HOST arrays of 7. */
+int dg_timing_read(dg_ctx* ctx, double ms[7], int64_t count[7]);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,7 @@ int hip_fail(int err, const char* what) {
 }
 
 // Per-launch HIP-event timing (dg_set_timing).
-enum { TK_TRACE = 0, TK_STAGE = 1, TK_RHS = 2, TK_VJP = 3, TK_RED = 4, TK_STAGE_FIRST = 5, TK_NKIND = 6 };
+enum { TK_TRACE = 0, TK_STAGE = 1, TK_RHS = 2, TK_VJP = 3, TK_RED = 4, TK_STAGE_FIRST = 5, TK_VISC = 6, TK_NKIND = 7 };
 constexpr size_t kMaxTimed = 65536;
 
 struct DGTiming {
@@ -208,10 +208,35 @@ int stages_nb(dg_ctx* c, double* Q, double* res, double dt, int s0, int count, d
   return DG_OK;
 }
 
+// Inviscid rate R = dQ/dt of the Euler terms by the neighbour-read kernel
+// (bitwise the same as the trace-buffer form).
+int euler_rate_nb(dg_ctx* c, const double* Q, double* R) {
+  return c->precision == DG_FP32_MFMA ? dg_launch_stage_nb_f32(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0)
+                                      : dg_launch_stage_nb(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0);
+}
+
+// Navier-Stokes stages: per stage the inviscid rate into the workspace, then
+// the viscous flux and the viscous rate, combined with the inviscid one into
+// the LSERK45 update of Q and res in place.
+int stages_visc(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
+  const DGWorkspace L = dg_workspace_layout(c);
+  double* R = (double*)(c->ws + L.off_visc_r);
+  double* Fv = (double*)(c->ws + L.off_visc_fv);
+  for (int g = 0; g < count; ++g) {
+    const int s = (s0 + g) % 5;
+    int err = timed(c, TK_RHS, [&] { return euler_rate_nb(c, Q, R); });
+    if (err) return hip_fail(err, "inviscid rate launch");
+    err = timed(c, TK_VISC, [&] { return dg_launch_visc(c, Q, Fv, R, Q, res, 1, kRKA[s], kRKB[s], dt, s == 0); });
+    if (err) return hip_fail(err, "viscous stage launch");
+  }
+  return DG_OK;
+}
+
 int stages(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
   // Traces of the initial Q, then `count` stages starting at stage s0; each
   // stage but the last writes the traces of its updated Q for the next.
   const bool f32 = c->precision == DG_FP32_MFMA;
+  if (c->mu > 0.0) return stages_visc(c, Q, res, dt, s0, count);
   if (c->exchange == DG_EXCHANGE_NEIGHBOUR) return stages_nb(c, Q, res, dt, s0, count);
   int err = timed(c, TK_TRACE, [&] {
     return f32 ? dg_launch_trace_f32(c, Q, (char*)trace_buf(c, 0)) : dg_launch_trace(c, Q, trace_buf(c, 0));
@@ -358,6 +383,11 @@ DGWorkspace dg_workspace_layout(const dg_ctx* c) {
   const size_t vjp_bytes = 2 * align256(DG_NF * N3 * (size_t)c->E * sizeof(double));
   L.off_q2 = L.off_vjp + vjp_bytes;
   L.total = L.off_q2 + align256(DG_NF * N3 * (size_t)c->E * sizeof(double));
+  L.off_visc_r = L.off_visc_fv = L.total;
+  if (c->mu > 0.0) {
+    L.off_visc_fv = L.off_visc_r + align256(DG_NF * N3 * (size_t)c->E * sizeof(double));
+    L.total = L.off_visc_fv + align256(12 * N3 * (size_t)c->E * sizeof(double));
+  }
   return L;
 }
 
@@ -410,6 +440,9 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
   c->xcd_remap = 1;
   c->pencil_x = 16;
   c->pencil_z = 8;
+  c->mu = 0.0;
+  c->prandtl = 0.72;
+  c->kappa = 0.0;
   c->epoch = 1;
   c->gstream = nullptr;
   c->ev_in = c->ev_out = nullptr;
@@ -444,7 +477,7 @@ int dg_set_timing(dg_ctx* c, int on) {
   return DG_OK;
 }
 
-int dg_timing_read(dg_ctx* c, double ms[6], int64_t count[6]) {
+int dg_timing_read(dg_ctx* c, double ms[7], int64_t count[7]) {
   if (!c) return fail(DG_EINVAL, "NULL context");
   if (!ms || !count) return fail(DG_EINVAL, "NULL output");
   for (int k = 0; k < TK_NKIND; ++k) {
@@ -497,6 +530,18 @@ int dg_set_precision(dg_ctx* c, int mode) {
     return DG_OK;
   }
   return fail(DG_EINVAL, "unknown precision mode %d", mode);
+}
+
+int dg_set_viscosity(dg_ctx* c, double mu, double prandtl) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(DG_EINVAL, "viscosity must be finite and >= 0 (got %g)", mu);
+  if (!(prandtl > 0.0) || !std::isfinite(prandtl))
+    return fail(DG_EINVAL, "Prandtl number must be finite and > 0 (got %g)", prandtl);
+  c->mu = mu;
+  c->prandtl = prandtl;
+  c->kappa = mu * (c->gamma / (c->gamma - 1.0)) / prandtl;
+  ++c->epoch;
+  return DG_OK;
 }
 
 int dg_set_option(dg_ctx* c, int key, int value) {
@@ -581,6 +626,14 @@ int dg_rhs(dg_ctx* c, const double* Q, double* R) {
   rc = check_state_pair(c, Q, "Q", R, "R");
   if (rc) return rc;
   const bool f32 = c->precision == DG_FP32_MFMA;
+  if (c->mu > 0.0) {
+    int err = timed(c, TK_RHS, [&] { return euler_rate_nb(c, Q, R); });
+    if (err) return hip_fail(err, "rhs launch");
+    double* Fv = (double*)(c->ws + dg_workspace_layout(c).off_visc_fv);
+    err = timed(c, TK_VISC, [&] { return dg_launch_visc(c, Q, Fv, R, nullptr, nullptr, 0, 0.0, 0.0, 0.0, 0); });
+    if (err) return hip_fail(err, "viscous rate launch");
+    return DG_OK;
+  }
   if (c->exchange == DG_EXCHANGE_NEIGHBOUR) {
     int err = timed(c, TK_RHS, [&] {
       return f32 ? dg_launch_stage_nb_f32(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0)
@@ -630,6 +683,7 @@ int dg_rk_steps_noalloc(dg_ctx* c, double* Q, double* res, double dt, int nsteps
   if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
   int rc = check_state_pair(c, Q, "Q", res, "res");
   if (rc) return rc;
+  if (c->mu > 0.0) return fail(DG_EUNSUPPORTED, "dg_rk_steps_noalloc covers the Euler terms only (viscosity is set)");
   if (state_bytes(c) > kScratchBytes)
     return fail(DG_EUNSUPPORTED, "state of %zu bytes exceeds the %zu-byte static buffer of dg_rk_steps_noalloc",
                 state_bytes(c), kScratchBytes);
@@ -649,7 +703,7 @@ int dg_rk_graph_steps(dg_ctx* c, double* Q, double* res, double dt, int nsteps) 
   rc = check_state_pair(c, Q, "Q", res, "res");
   if (rc) return rc;
   if (nsteps == 0) return DG_OK;
-  if (c->exchange != DG_EXCHANGE_NEIGHBOUR) return stages(c, Q, res, dt, 0, 5 * nsteps);
+  if (c->exchange != DG_EXCHANGE_NEIGHBOUR || c->mu > 0.0) return stages(c, Q, res, dt, 0, 5 * nsteps);
   int err;
   if (!c->gstream) {
     err = (int)hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking);
@@ -720,6 +774,7 @@ int dg_rk_graph_steps(dg_ctx* c, double* Q, double* res, double dt, int nsteps) 
 int dg_rhs_vjp(dg_ctx* c, const double* Q, const double* gR, double* gQ) {
   int rc = check_ready(c);
   if (rc) return rc;
+  if (c->mu > 0.0) return fail(DG_EUNSUPPORTED, "the adjoint covers the Euler terms only (viscosity is set)");
   if (!Q || !gR || !gQ) return fail(DG_EINVAL, "NULL array");
   if (misaligned(Q) || misaligned(gR) || misaligned(gQ)) return fail(DG_EINVAL, "arrays must be 8-byte aligned");
   if (overlap(Q, gQ, state_bytes(c))) return fail(DG_EALIAS, "gQ overlaps Q");
@@ -732,6 +787,7 @@ int dg_rhs_vjp(dg_ctx* c, const double* Q, const double* gR, double* gQ) {
 int dg_rk_stage_vjp(dg_ctx* c, int s, const double* Qs, double* gQ, double* gres, double dt) {
   int rc = check_ready(c);
   if (rc) return rc;
+  if (c->mu > 0.0) return fail(DG_EUNSUPPORTED, "the adjoint covers the Euler terms only (viscosity is set)");
   if (s < 0 || s > 4) return fail(DG_EINVAL, "stage must be 0..4 (got %d)", s);
   if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
   if (!Qs || !gQ || !gres) return fail(DG_EINVAL, "NULL array");

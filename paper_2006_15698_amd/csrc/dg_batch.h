@@ -12,13 +12,26 @@ struct DGBatchInst {
   double dt;         // time step of this mesh
 };
 
+// How the persistent grid shares out the work list.  Workgroups are dealt to
+// the 8 XCDs round robin (workgroup w runs on XCD w % 8).  With xcd = 1 the
+// list is cut into 8 contiguous parts of about equal work, bounds[x] ..
+// bounds[x + 1], and the workgroups of XCD x walk part x round robin, so the
+// items that run at the same time on one XCD are neighbours in the list (and
+// their neighbour reads meet in that XCD's L2).  With xcd = 0 every
+// workgroup walks the whole list round robin.
+struct DGBatchSplit {
+  int xcd;
+  int bounds[9];
+};
+
 struct DGBatchLaunch {
   const DGBatchInst* inst;
   const int2* items;  // (mesh, first element)
   int nitems;
-  unsigned grid;
+  unsigned grid;      // a multiple of 8 when split.xcd is set
   hipStream_t stream;
   int f32;
+  DGBatchSplit split;
 };
 
 int dg_batch_tile_list(int N, int* out, int max);

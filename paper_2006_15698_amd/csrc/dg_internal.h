@@ -52,6 +52,9 @@ struct dg_ctx {
   int order;      // DG_ORDER_LINEAR or DG_ORDER_PENCIL
   int pencil_x;   // pencil extent along x in elements (0: whole row)
   int pencil_z;   // pencil extent along z in element planes
+  // viscous terms (dg_set_viscosity): dynamic viscosity, Prandtl number and
+  // conductivity mu gamma / ((gamma - 1) Pr); mu = 0 is the Euler equations
+  double mu, prandtl, kappa;
   // graph replay of whole steps (dg_rk_graph_steps): one executable graph
   // per ping-pong parity, valid while the arrays, dt and `epoch` (bumped by
   // every setter that changes what a launch does) are unchanged
@@ -99,6 +102,8 @@ struct DGWorkspace {
   size_t off_red;       // reduction partials
   size_t off_vjp;       // adjoint scratch: two state-sized buffers
   size_t off_q2;        // second state buffer of the neighbour-read path
+  size_t off_visc_r;    // viscous terms only (mu > 0): the inviscid rate of a stage (5 N^3 E doubles)
+  size_t off_visc_fv;   //   and the nodal viscous flux (12 N^3 E doubles)
   size_t total;
 };
 DGWorkspace dg_workspace_layout(const dg_ctx* c);
@@ -126,6 +131,12 @@ int dg_launch_stage_nb(const dg_ctx* c, const double* Qin, double* Qout, double*
 int dg_launch_reduce(const dg_ctx* c, const double* Q, double* red);
 // Adjoint RHS.
 int dg_launch_vjp(const dg_ctx* c, const double* Q, const double* gR, double* gQ, char* scratch);
+
+// Viscous terms (kern_visc.hip): the nodal viscous flux of Q into Fv, then
+// mode 0: R += the viscous rate; mode 1: the LSERK45 stage in place on Qu
+// and res with R the inviscid rate of the stage.
+int dg_launch_visc(const dg_ctx* c, const double* Q, double* Fv, double* R, double* Qu, double* res, int mode,
+                   double a, double b, double dt, int first);
 
 // Gradient of the kinetic-energy integral with respect to Q.
 int dg_launch_ke_grad(const dg_ctx* c, const double* Q, double* G);

@@ -71,11 +71,18 @@ __device__ __forceinline__ void run_item(const DGBatchInst& I, int e0, const dou
 
 template <int MODE, bool F32>
 __global__ void __launch_bounds__(BNT)
-k_batch_stage(const DGBatchInst* __restrict__ inst, const int2* __restrict__ items, int nitems,
+k_batch_stage(const DGBatchInst* __restrict__ inst, const int2* __restrict__ items, int nitems, DGBatchSplit split,
               const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR, double a,
               double b, int first) {
   __shared__ double smem[F32 ? kSmem32 : kSmem64];
-  for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+  int k0 = blockIdx.x, kend = nitems, kstep = gridDim.x;
+  if (split.xcd) {
+    const int x = blockIdx.x & 7;
+    k0 = split.bounds[x] + (blockIdx.x >> 3);
+    kend = split.bounds[x + 1];
+    kstep = gridDim.x >> 3;
+  }
+  for (int k = k0; k < kend; k += kstep) {
     const int2 w = items[k];
     const int mi = __builtin_amdgcn_readfirstlane(w.x);
     const int e0 = __builtin_amdgcn_readfirstlane(w.y);
@@ -104,7 +111,7 @@ int dg_batch_launch_stage(const DGBatchLaunch& L, int mode, const double* Qin, d
                           double b, int first) {
 #define DG_L(m, f)                                                                                           \
   hipLaunchKernelGGL((k_batch_stage<m, f>), dim3(L.grid), dim3(BNT), 0, L.stream, L.inst, L.items, L.nitems, \
-                     Qin, Qout, RR, a, b, first)
+                     L.split, Qin, Qout, RR, a, b, first)
   if (L.f32) {
     if (mode == 0) DG_L(0, true);
     else DG_L(1, true);

@@ -1,0 +1,229 @@
+// Viscous (Navier-Stokes) terms on the collocated Gauss-Legendre basis:
+// Bassi & Rebay's first scheme (BR1).
+//
+// The paper names the viscous formulation of its CPU code (Section III,
+// Fig. 2) without printing it; the reading taken (constant mu, Stokes'
+// hypothesis, Fourier conduction at constant Prandtl number, gas constant 1
+// so T = p / rho):
+//   theta_d = grad_d of the primitive quantities P = (u, v, w, T), the weak
+//             derivative of their nodal interpolants with the central mean
+//             of the two sides' traces on every face;
+//   F_v^d   = (0, tau_1d, tau_2d, tau_3d, u_k tau_kd + kappa dT/dx_d),
+//             tau_kd = mu (du_k/dx_d + du_d/dx_k - 2/3 delta_kd div u),
+//             evaluated at the nodes;
+//   dQ/dt  += the weak derivative of F_v^d's nodal interpolant with the
+//             central mean of the two sides' traces, summed over d.
+// Both weak derivatives have the form, along the d-line of node i (the mass
+// matrix divided out, as in the inviscid stage):
+//   (2/h_d) [ -sum_a Dh[i][a] X_a + l_i(+1)/w_i {X}_+ - l_i(-1)/w_i {X}_- ].
+//
+// Two launches per right-hand side, one workgroup per element, one thread
+// per node:
+//   k_visc_flux  Q -> F_v at every node (12 values: 4 per direction);
+//                the neighbours' primitive traces are interpolated from
+//                their state in the same launch;
+//   k_visc_apply F_v -> the viscous rate, added to the inviscid rate R that
+//                the inviscid stage kernel wrote (MODE 0), or combined with
+//                it into the LSERK45 update of Q and res in place (MODE 1:
+//                no launch reads another element's Q here).
+
+#include "dg_internal.h"
+#include "stage_fp64.h"
+
+namespace {
+
+template <int N>
+struct VCfg {
+  static constexpr int N2 = N * N;
+  static constexpr int N3 = N * N * N;
+  static constexpr int NT = N3 <= 64 ? 64 : (N3 + 63) / 64 * 64;
+};
+
+// (u, v, w, T) of a conserved state, T = p / rho with Eq. (3)'s pressure.
+__device__ __forceinline__ void primitive(const double* q, double gm1, double* P) {
+  const double r = dgdev::recip(q[0]);
+  P[0] = q[1] * r;
+  P[1] = q[2] * r;
+  P[2] = q[3] * r;
+  const double ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * r;
+  P[3] = gm1 * (q[4] - ke) * r;
+}
+
+// Tangential point index (lower tangential axis fastest) and position
+// along direction d of node (i, j, k).
+template <int N>
+__device__ __forceinline__ void line_of(int d, int i, int j, int k, int& m, int& pt) {
+  if (d == 0) { m = i; pt = j + N * k; }
+  else if (d == 1) { m = j; pt = i + N * k; }
+  else { m = k; pt = i + N * j; }
+}
+
+// BR1 weak derivative along the d-line through node position m0 of the
+// field X (LDS, N^3 values): own traces from the line, neighbour traces
+// tm (on the -d face) and tp (on the +d face) given.
+template <int N>
+__device__ __forceinline__ double br1_line(const DGTables& tb, const double* X, int d, int m0, int pt, double tm,
+                                           double tp) {
+  double own_m = 0.0, own_p = 0.0, vol = 0.0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const double x = X[dgdev::tnode<N>(d, a, pt)];
+    own_m = fma(tb.lm[a], x, own_m);
+    own_p = fma(tb.lp[a], x, own_p);
+    vol = fma(tb.Dh[m0 * N + a], x, vol);
+  }
+  const double hat_m = 0.5 * (own_m + tm);
+  const double hat_p = 0.5 * (own_p + tp);
+  return tb.sc[d] * (tb.liftp[m0] * hat_p - tb.liftm[m0] * hat_m - vol);
+}
+
+template <int N>
+__global__ void __launch_bounds__(VCfg<N>::NT)
+k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, double mu, double kappa) {
+  constexpr int N2 = VCfg<N>::N2, N3 = VCfg<N>::N3, NT = VCfg<N>::NT;
+  __shared__ double P[4][N3];
+  __shared__ double Tn[6][4][N2];   // face 2d + s: neighbour's trace (s = 0: -d face, 1: +d face)
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const int64_t fs = (int64_t)tb.E * N3;
+  if (t < N3) {
+    double q[5], p[4];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) q[f] = Q[f * fs + (int64_t)e * N3 + t];
+    primitive(q, tb.gm1, p);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) P[c][t] = p[c];
+  }
+  for (int fp = t; fp < 6 * N2; fp += NT) {
+    const int face = fp / N2, pt = fp % N2, d = face >> 1, s = face & 1;
+    const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < N; ++m) {
+      const int64_t g = (int64_t)en * N3 + dgdev::tnode<N>(d, m, pt);
+      double q[5], p[4];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) q[f] = Q[f * fs + g];
+      primitive(q, tb.gm1, p);
+      const double wgt = s ? tb.lm[m] : tb.lp[m];   // the +d neighbour's -d face, the -d neighbour's +d face
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = fma(wgt, p[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
+  }
+  __syncthreads();
+  if (t >= N3) return;
+  const int i = t % N, j = (t / N) % N, k = t / N2;
+  double th[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int m0, pt;
+    line_of<N>(d, i, j, k, m0, pt);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) th[d][c] = br1_line<N>(tb, P[c], d, m0, pt, Tn[2 * d][c][pt], Tn[2 * d + 1][c][pt]);
+  }
+  const double u[3] = {P[0][t], P[1][t], P[2][t]};
+  const double div = th[0][0] + th[1][1] + th[2][2];
+  const int64_t g = (int64_t)e * N3 + t;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double en = kappa * th[d][3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      double tau = mu * (th[d][kk] + th[kk][d]);
+      if (kk == d) tau = tau - (2.0 / 3.0) * mu * div;
+      Fv[(d * 4 + kk) * fs + g] = tau;
+      en = en + u[kk] * tau;
+    }
+    Fv[(d * 4 + 3) * fs + g] = en;
+  }
+}
+
+// MODE 0: R += viscous rate.  MODE 1: LSERK45 stage in place with the
+// inviscid rate R: res = a res + dt (R + viscous) (first stage: res =
+// dt (R + viscous)), Q = Q + b res.
+template <int N, int MODE>
+__global__ void __launch_bounds__(VCfg<N>::NT)
+k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R, double* __restrict__ Q,
+             double* __restrict__ res, double a, double b, double dt, int first) {
+  constexpr int N2 = VCfg<N>::N2, N3 = VCfg<N>::N3, NT = VCfg<N>::NT;
+  __shared__ double F[12][N3];
+  __shared__ double Tn[6][4][N2];
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const int64_t fs = (int64_t)tb.E * N3;
+  if (t < N3) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) F[c][t] = Fv[c * fs + (int64_t)e * N3 + t];
+  }
+  for (int fp = t; fp < 6 * N2; fp += NT) {
+    const int face = fp / N2, pt = fp % N2, d = face >> 1, s = face & 1;
+    const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < N; ++m) {
+      const int64_t g = (int64_t)en * N3 + dgdev::tnode<N>(d, m, pt);
+      const double wgt = s ? tb.lm[m] : tb.lp[m];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = fma(wgt, Fv[(d * 4 + c) * fs + g], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
+  }
+  __syncthreads();
+  if (t >= N3) return;
+  const int i = t % N, j = (t / N) % N, k = t / N2;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int m0, pt;
+    line_of<N>(d, i, j, k, m0, pt);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      v[1 + c] += br1_line<N>(tb, F[d * 4 + c], d, m0, pt, Tn[2 * d][c][pt], Tn[2 * d + 1][c][pt]);
+  }
+  const int64_t g = (int64_t)e * N3 + t;
+  if (MODE == 0) {
+#pragma unroll
+    for (int f = 1; f < 5; ++f) R[f * fs + g] += v[f];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const double rate = R[f * fs + g] + v[f];
+      const double r = first ? dt * rate : fma(a, res[f * fs + g], dt * rate);
+      res[f * fs + g] = r;
+      Q[f * fs + g] = fma(b, r, Q[f * fs + g]);
+    }
+  }
+}
+
+template <int N>
+int launch_visc_n(const dg_ctx* c, const double* Q, double* Fv, double* R, double* Qu, double* res, int mode,
+                  double a, double b, double dt, int first) {
+  const unsigned grid = (unsigned)c->E;
+  const dim3 blk(VCfg<N>::NT);
+  hipLaunchKernelGGL(k_visc_flux<N>, dim3(grid), blk, 0, c->stream, c->tab, Q, Fv, c->mu, c->kappa);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_visc_apply<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, nullptr, nullptr, a, b,
+                       dt, first);
+  else
+    hipLaunchKernelGGL((k_visc_apply<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, Qu, res, a, b, dt,
+                       first);
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int dg_launch_visc(const dg_ctx* c, const double* Q, double* Fv, double* R, double* Qu, double* res, int mode,
+                   double a, double b, double dt, int first) {
+  switch (c->N) {
+    case 1: return launch_visc_n<1>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    case 2: return launch_visc_n<2>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    case 3: return launch_visc_n<3>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    case 4: return launch_visc_n<4>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    case 5: return launch_visc_n<5>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    case 6: return launch_visc_n<6>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    case 7: return launch_visc_n<7>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    case 8: return launch_visc_n<8>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    default: return (int)hipErrorInvalidValue;
+  }
+}

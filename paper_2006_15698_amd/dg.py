@@ -62,6 +62,7 @@ _SIGS = {
     "dg_set_domain": (_i, [_vp, _d, _d, _d]),
     "dg_set_stream": (_i, [_vp, _vp]),
     "dg_set_precision": (_i, [_vp, _i]),
+    "dg_set_viscosity": (_i, [_vp, _d, _d]),
     "dg_workspace_bytes": (_sz, [_vp]),
     "dg_set_workspace": (_i, [_vp, _vp, _sz]),
     "dg_num_dof": (_i64, [_vp]),
@@ -84,6 +85,8 @@ _SIGS = {
     "dg_batch_set_stream": (_i, [_vp, _vp]),
     "dg_batch_set_precision": (_i, [_vp, _i]),
     "dg_batch_set_tile": (_i, [_vp, _i, _i]),
+    "dg_batch_set_option": (_i, [_vp, _i, _i]),
+    "dg_batch_get_option": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_int)]),
     "dg_batch_tile_options": (_i, [_i, ctypes.POINTER(ctypes.c_int), _i]),
     "dg_batch_offset": (_i64, [_vp, _i]),
     "dg_batch_workspace_bytes": (_sz, [_vp]),
@@ -172,6 +175,10 @@ def dg_set_stream(ctx, stream=None):
 
 def dg_set_precision(ctx, mode):
     return _check(_lib.dg_set_precision(ctx, int(mode)))
+
+
+def dg_set_viscosity(ctx, mu, prandtl=0.72):
+    return _check(_lib.dg_set_viscosity(ctx, float(mu), float(prandtl)))
 
 
 def dg_set_option(ctx, key, value):
@@ -286,7 +293,7 @@ def dg_check_state(ctx, Q):
     return True
 
 
-TIMING_KINDS = ("trace", "stage", "rhs", "vjp", "reduce", "stage_first")
+TIMING_KINDS = ("trace", "stage", "rhs", "vjp", "reduce", "stage_first", "visc")
 
 
 def dg_set_timing(ctx, on):
@@ -328,6 +335,16 @@ def dg_batch_set_precision(b, mode):
 
 def dg_batch_set_tile(b, p, epb):
     return _check(_lib.dg_batch_set_tile(b, int(p), int(epb)))
+
+
+def dg_batch_set_option(b, key, value):
+    return _check(_lib.dg_batch_set_option(b, int(key), int(value)))
+
+
+def dg_batch_get_option(b, key):
+    v = ctypes.c_int(0)
+    _check(_lib.dg_batch_get_option(b, int(key), ctypes.byref(v)))
+    return v.value
 
 
 def dg_batch_tile_options(p):
@@ -420,6 +437,16 @@ class Batch:
     def _s(self):
         dg_batch_set_stream(self.b, None)
 
+    def set_option(self, key, value):
+        """Work-list visiting order (DG_OPT_XCD_REMAP, DG_OPT_ORDER,
+        DG_OPT_PENCIL_X, DG_OPT_PENCIL_Z); results are bitwise unchanged."""
+        self._s()
+        dg_batch_set_option(self.b, key, value)
+
+    def options(self):
+        return {name: dg_batch_get_option(self.b, k) for k, name in OPTION_NAMES.items()
+                if k != DG_OPT_EXCHANGE}
+
     def set_dt(self, dt):
         self._s()
         dg_batch_set_dt(self.b, dt)
@@ -443,7 +470,7 @@ class Solver:
     """One periodic mesh on one GPU: owns the context and a torch-allocated
     workspace, and enqueues every call on the current torch stream."""
 
-    def __init__(self, n, p, L=(1.0, 1.0, 1.0), gamma=1.4, precision=DG_FP64, device=None):
+    def __init__(self, n, p, L=(1.0, 1.0, 1.0), gamma=1.4, precision=DG_FP64, device=None, mu=0.0, prandtl=0.72):
         import torch
         if isinstance(n, int):
             n = (n, n, n)
@@ -456,11 +483,27 @@ class Solver:
         self.ctx = dg_create(*self.n, self.p, self.gamma)
         dg_set_domain(self.ctx, *self.L)
         dg_set_precision(self.ctx, precision)
+        self.mu, self.prandtl = float(mu), float(prandtl)
+        dg_set_viscosity(self.ctx, self.mu, self.prandtl)
+        self.workspace = None
+        self._workspace()
+
+    def _workspace(self):
+        """(Re)allocate the workspace the current settings need."""
+        import torch
         nbytes = dg_workspace_bytes(self.ctx)
+        if self.workspace is not None and self.workspace.numel() >= nbytes + 256:
+            return
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         addr = self.workspace.data_ptr()
         aligned = (addr + 255) & ~255
         _check(_lib.dg_set_workspace(self.ctx, aligned, nbytes))
+
+    def set_viscosity(self, mu, prandtl=0.72):
+        """Navier-Stokes terms with dynamic viscosity mu (0: Euler)."""
+        self.mu, self.prandtl = float(mu), float(prandtl)
+        dg_set_viscosity(self.ctx, self.mu, self.prandtl)
+        self._workspace()
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -532,7 +575,9 @@ class Solver:
         return dg_max_wavespeed(self.ctx, Q)
 
     def dt_cfl(self, Q, cfl):
-        """dt = CFL / ((2p+1) max_d-summed wave rate), computed on the GPU."""
+        """dt = CFL / ((2p+1) max_d-summed wave rate), computed on the GPU
+        (the inviscid limit; with viscosity the caller adds any viscous
+        limit)."""
         return cfl / ((2 * self.p + 1) * self.max_wavespeed(Q))
 
     def check_state(self, Q):

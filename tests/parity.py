@@ -54,3 +54,49 @@ def patch_rhs(n, p, L, Q, elems, gamma=1.4):
         R = small.rhs(np.ascontiguousarray(patch))
         out[(ex, ey, ez)] = R[:, 1, 1, 1]
     return out
+
+
+def visc_summand_scale(ns, Q):
+    """Per field: the summand scale of the viscous rate, max over nodes of
+    sum_d (2/h_d) |F_v^d_f| times max_i sum_a |w_a D_ai / w_i| (F_v the
+    oracle's nodal viscous flux), plus the same for the gradients that
+    F_v is built from, scaled by the viscosity."""
+    xi, w = gauss_legendre(ns.N)
+    dh = 1.0
+    if ns.N > 1:
+        D = lagrange_deriv(xi, xi)
+        dh = max(1.0, float(np.max(np.sum(np.abs(w[:, None] * D / w[None, :]), axis=0))))
+    th = ns.gradients(Q)
+    Fv = ns.viscous_flux(Q, th)
+    s = np.zeros(Fv.shape[1:])
+    for d in range(3):
+        s = s + (2.0 / ns.h[d]) * np.abs(Fv[d])
+    out = np.max(s.reshape(5, -1), axis=1) * dh
+    # the gradients' own summands enter every stress through mu (and the
+    # energy through kappa): (2/h)^2 times the largest primitive magnitude
+    P = np.abs(ns.primitives(Q)).reshape(4, -1).max(axis=1)
+    g = (2.0 / ns.h.min()) ** 2 * dh * dh
+    out[1:4] += ns.mu * g * P[:3].max()
+    out[4] += (ns.kappa * P[3] + ns.mu * P[:3].max() ** 2) * g
+    return out
+
+
+def patch_rhs_viscous(n, p, L, Q, elems, mu, prandtl, gamma=1.4):
+    """Oracle Navier-Stokes right-hand side at selected elements of a large
+    periodic mesh: the viscous rate of an element depends on the elements
+    within two face steps of it (the gradients of its face neighbours use
+    their neighbours), so it equals the rate of the centre element of the
+    5x5x5 periodic patch around it.  Returns {(ex,ey,ez): R[5,N,N,N]}."""
+    from oracle.viscous import NavierStokesDG
+    nx, ny, nz = n
+    h = np.array(L, dtype=np.float64) / np.array(n)
+    small = NavierStokesDG((5, 5, 5), p, L=tuple(5 * h), gamma=gamma, mu=mu, prandtl=prandtl)
+    out = {}
+    for (ex, ey, ez) in elems:
+        xs = [(ex + o) % nx for o in range(-2, 3)]
+        ys = [(ey + o) % ny for o in range(-2, 3)]
+        zs = [(ez + o) % nz for o in range(-2, 3)]
+        patch = Q[:, zs][:, :, ys][:, :, :, xs]
+        R = small.rhs(np.ascontiguousarray(patch))
+        out[(ex, ey, ez)] = R[:, 2, 2, 2]
+    return out

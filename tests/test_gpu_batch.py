@@ -133,3 +133,27 @@ def test_batch_errors(dgm):
             dgm.dg_batch_rk_steps(b, Q, Q.clone(), 1)     # no workspace yet
     finally:
         dgm.dg_batch_destroy(b)
+
+
+def test_batch_visiting_orders_bitwise_equal(dgm):
+    """Every work-list order (row or pencil order inside a mesh, XCD split
+    on or off, ragged pencils) gives bitwise the same steps."""
+    import torch
+    specs = _specs(12, 19, 2, 7)
+    b, states, Q0 = _setup(dgm, specs)
+    b.set_dt(_dts(specs, states))
+    ref = None
+    for xcd, order, px, pz in [(0, dgm.DG_ORDER_LINEAR, 0, 1), (1, dgm.DG_ORDER_LINEAR, 0, 1),
+                               (0, dgm.DG_ORDER_PENCIL, 3, 2), (1, dgm.DG_ORDER_PENCIL, 16, 8),
+                               (1, dgm.DG_ORDER_PENCIL, 5, 3)]:
+        b.set_option(dgm.DG_OPT_XCD_REMAP, xcd)
+        b.set_option(dgm.DG_OPT_ORDER, order)
+        b.set_option(dgm.DG_OPT_PENCIL_X, px)
+        b.set_option(dgm.DG_OPT_PENCIL_Z, pz)
+        assert b.options()["xcd_remap"] == xcd and b.options()["pencil_z"] == pz
+        Q, r = Q0.clone(), torch.zeros_like(Q0)
+        b.step(Q, r, nsteps=2, graph=True)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = Q
+        assert torch.equal(Q, ref), (xcd, order, px, pz)

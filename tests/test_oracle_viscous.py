@@ -214,3 +214,18 @@ def test_one_dimensional_reduction(p):
     # every other line is the same, and there is no y/z momentum rate
     assert np.max(np.abs(R - R[:, :1, :1, :, :1, :1, :])) <= 1e-12 * scale
     assert np.max(np.abs(R[2:4])) <= 1e-12 * scale
+
+
+def test_rate_of_an_element_depends_on_two_face_steps_only():
+    """The 5x5x5 periodic patch around an element gives its Navier-Stokes
+    rate exactly (the check that GPU tests on large meshes rely on); the
+    3x3x3 patch of the Euler terms does not suffice once mu > 0."""
+    from tests.parity import patch_rhs_viscous
+    n, p, L = (7, 6, 6), 2, (1.0, 0.9, 1.1)
+    mu, pr = 0.05, 0.7
+    Q = W.random_smooth(n, p, seed=31, L=L, noise=0.05)
+    full = NavierStokesDG(n, p, L=L, mu=mu, prandtl=pr).rhs(Q)
+    elems = [(0, 0, 0), (3, 2, 4), (6, 5, 5)]
+    got = patch_rhs_viscous(n, p, L, Q, elems, mu, pr)
+    for (ex, ey, ez), R in got.items():
+        assert np.max(np.abs(R - full[:, ez, ey, ex])) <= 1e-12 * np.max(np.abs(full))
