@@ -35,6 +35,8 @@ WORKLOADS = {
                              "dt from CFL 0.3, 100 LSERK45 steps"),
     "tgv48_p4": (48, 4, 50, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 48^3 elements, p=4 "
                             "(one GPU's share at the paper's per-GPU size), 50 LSERK45 steps"),
+    "tgv48_p4_re1600": (48, 4, 50, "viscous Taylor-Green vortex (Navier-Stokes, BR1 viscous terms), [0,2pi]^3, "
+                                   "Mach 0.1, Re 1600 (mu = 1/1600, Pr 0.71), 48^3 elements, p=4, 50 LSERK45 steps"),
     "tgv40_p6": (40, 6, 100, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 40^3 elements, p=6 "
                              "(the paper's degree), 100 LSERK45 steps"),
     "adjoint16_p3": (16, 3, 40, "gradient of the integrated kinetic energy after 40 LSERK45 steps with respect to "
@@ -46,6 +48,15 @@ WORKLOADS = {
                                  "p uniform in 1..5, amplitudes uniform in [0.05,0.3], each mesh with "
                                  "its own CFL-0.3 dt; one graph-replayed launch per RK stage"),
 }
+
+
+# Viscous workloads: (dynamic viscosity, Prandtl number).
+VISCOUS = {"tgv48_p4_re1600": (1.0 / 1600.0, 0.71)}
+# Bytes per node and stage of the viscous decomposition (FP64, 5 fields, 12
+# viscous-flux values): the inviscid rate (read Q, write R) 80; k_visc_flux
+# (read Q, write the flux) 136; k_visc_apply (read the flux, R, Q, res; write
+# Q, res) 296.
+VISC_BYTES = {"rhs": 80, "visc": 136 + 296}
 
 
 def flops_per_dof_stage(N):
@@ -71,6 +82,7 @@ STAGE_SOURCES = {
                                                 "paper_2006_15698_amd/csrc/kern_batch.hip",
                                                 "paper_2006_15698_amd/csrc/batch_api.cpp"],
     "vjp": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_vjp.hip"],
+    "visc": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_visc.hip"],
 }
 
 
@@ -109,21 +121,33 @@ def measured_traffic(workload, family, options):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(n, p, L, budget_s):
+def cpu_baseline(n, p, L, budget_s, viscous=None):
     """The oracle (plain dense FP64 numpy) advancing RK stages of the same
-    workload on the host for about ``budget_s`` seconds."""
+    workload on the host for about ``budget_s`` seconds.  With viscosity
+    (mu, Pr) the Navier-Stokes oracle runs on a 16^3-element periodic block
+    of the same element size and degree (its cost per node is that of the
+    whole mesh; one stage of the full 48^3 mesh takes minutes)."""
     import numpy as np
     import workloads as W
     from oracle import lserk
     from oracle.dg import DG
+    from oracle.viscous import NavierStokesDG
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()
                        if i.get("user_api") == "blas"] or [1])
     except Exception:
         threads = os.cpu_count()
-    ora = DG((n, n, n), p, L=L)
-    Q = W.tgv(n, p)
+    sample = ""
+    if viscous is None:
+        ora = DG((n, n, n), p, L=L)
+        Q = W.tgv(n, p)
+    else:
+        m = min(n, 16)
+        Lm = tuple(Ld * m / n for Ld in L)
+        ora = NavierStokesDG((m, m, m), p, L=Lm, mu=viscous[0], prandtl=viscous[1])
+        Q = W.tgv(m, p, L=Lm)
+        sample = f"a {m}^3-element block of the same element size and degree: "
     res = np.zeros_like(Q)
     dt = ora.dt_cfl(Q, 0.3)
     t0 = time.perf_counter()
@@ -137,7 +161,7 @@ def cpu_baseline(n, p, L, budget_s):
     dof = ora.num_dof()
     return {"value": dof * stages / el / 1e9, "unit": "GDOF-RK-stages/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{stages} RK stages of the same workload ({dof} nodes) in {el:.1f} s; "
+            "sample": f"{sample}{stages} RK stages of the same workload ({dof} nodes) in {el:.1f} s; "
                       f"BLAS threads {threads}, host cpu_count {os.cpu_count()}"}
 
 
@@ -440,7 +464,9 @@ def main():
     Wm = args.warmup
     L = (2 * math.pi,) * 3
     prec = dg.DG_FP64 if args.precision == "fp64" else dg.DG_FP32_MFMA
-    s = dg.Solver((n, n, n), p, L=L, precision=prec)
+    viscous = VISCOUS.get(args.workload)
+    mu, prandtl = viscous if viscous else (0.0, 0.72)
+    s = dg.Solver((n, n, n), p, L=L, precision=prec, mu=mu, prandtl=prandtl)
     s.set_option(dg.DG_OPT_EXCHANGE, dg.DG_EXCHANGE_NEIGHBOUR if args.exchange == "neighbour"
                  else dg.DG_EXCHANGE_TRACES)
     for key, val in ((dg.DG_OPT_XCD_REMAP, args.xcd_remap),
@@ -484,8 +510,35 @@ def main():
                    "dof": dof, "precision": args.precision, "dt": dt,
                    "options": s.options(), "graph_replay": graph},
     }
+    if viscous:
+        out["config"].update({"mu": mu, "prandtl": prandtl})
 
-    if not args.no_roofline:
+    if viscous and not args.no_roofline:
+        # Three launches per stage: the inviscid rate, then the viscous flux
+        # and the viscous rate with the RK update (timed together).  Average
+        # durations from the library's HIP events on its stream.
+        dg.dg_set_timing(s.ctx, True)
+        s.step(Q, res, dt, nsteps=K)
+        t = dg.dg_timing_read(s.ctx)
+        dg.dg_set_timing(s.ctx, False)
+        parts = {}
+        for kind, label in (("rhs", "inviscid rate (k_stage_nb, RHS mode)"),
+                            ("visc", "k_visc_flux + k_visc_apply")):
+            k_ms, k_n = t[kind]
+            a_s = k_ms / k_n * 1e-3
+            parts[kind] = {"kernel": label, "avg_launch_us": a_s * 1e6, "launches": k_n,
+                           "alg_bytes_per_launch": VISC_BYTES[kind] * dof,
+                           "achieved": VISC_BYTES[kind] * dof / a_s / 1e9}
+        v = parts["visc"]
+        out["roofline"] = {"bound": "hbm", "achieved": v["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": v["achieved"] / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(args.workload, "visc", s.options()),
+                           "kernel": "k_visc_flux + k_visc_apply (viscous terms and LSERK45 update, one stage)",
+                           "avg_launch_us": v["avg_launch_us"], "launches": v["launches"],
+                           "alg_bytes_per_launch": v["alg_bytes_per_launch"],
+                           "inviscid_rate": parts["rhs"],
+                           "stage_bytes_per_node": sum(VISC_BYTES.values())}
+    elif not args.no_roofline:
         # Dominant kernel: the fused stage kernel of stages 2..5 (four of the
         # five launches of a step; the first stage's kernel, which does not
         # read the residual, is reported beside it).  Average launch duration
@@ -517,11 +570,11 @@ def main():
                             "frac": fl / avg_s / 1e12 / FP64_PEAK_TFS,
                             "flops_per_dof_stage": flops_per_dof_stage(p + 1)}
 
-    if not args.no_precision_clause:
+    if not args.no_precision_clause and not viscous:
         out["fp32_mfma_vs_fp64"] = precision_clause(args, n, p, L, Q0, dt, K, Wm, graph, value)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, p, L, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(n, p, L, args.cpu_seconds, viscous)
 
     print(json.dumps(out), flush=True)
 

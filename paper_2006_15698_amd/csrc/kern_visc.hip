@@ -24,8 +24,9 @@
 //                their state in the same launch;
 //   k_visc_apply F_v -> the viscous rate, added to the inviscid rate R that
 //                the inviscid stage kernel wrote (MODE 0), or combined with
-//                it into the LSERK45 update of Q and res in place (MODE 1:
-//                no launch reads another element's Q here).
+//                it into the LSERK45 update of Q and res in place (MODE 1,
+//                MODE 2 for the first stage: no launch reads another
+//                element's Q here).
 
 #include "dg_internal.h"
 #include "stage_fp64.h"
@@ -140,12 +141,14 @@ k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, 
 }
 
 // MODE 0: R += viscous rate.  MODE 1: LSERK45 stage in place with the
-// inviscid rate R: res = a res + dt (R + viscous) (first stage: res =
-// dt (R + viscous)), Q = Q + b res.
+// inviscid rate R: res = a res + dt (R + viscous), Q = Q + b res.  MODE 2:
+// the first stage (a = 0): res = dt (R + viscous) without reading res.  (A
+// runtime flag instead of MODE 2 made the compiler duplicate the body and
+// hold 200-250 registers.)
 template <int N, int MODE>
 __global__ void __launch_bounds__(VCfg<N>::NT)
 k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R, double* __restrict__ Q,
-             double* __restrict__ res, double a, double b, double dt, int first) {
+             double* __restrict__ res, double a, double b, double dt) {
   constexpr int N2 = VCfg<N>::N2, N3 = VCfg<N>::N3, NT = VCfg<N>::NT;
   __shared__ double F[12][N3];
   __shared__ double Tn[6][4][N2];
@@ -189,7 +192,7 @@ k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R,
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
       const double rate = R[f * fs + g] + v[f];
-      const double r = first ? dt * rate : fma(a, res[f * fs + g], dt * rate);
+      const double r = MODE == 2 ? dt * rate : fma(a, res[f * fs + g], dt * rate);
       res[f * fs + g] = r;
       Q[f * fs + g] = fma(b, r, Q[f * fs + g]);
     }
@@ -204,10 +207,11 @@ int launch_visc_n(const dg_ctx* c, const double* Q, double* Fv, double* R, doubl
   hipLaunchKernelGGL(k_visc_flux<N>, dim3(grid), blk, 0, c->stream, c->tab, Q, Fv, c->mu, c->kappa);
   if (mode == 0)
     hipLaunchKernelGGL((k_visc_apply<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, nullptr, nullptr, a, b,
-                       dt, first);
+                       dt);
+  else if (first)
+    hipLaunchKernelGGL((k_visc_apply<N, 2>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, Qu, res, a, b, dt);
   else
-    hipLaunchKernelGGL((k_visc_apply<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, Qu, res, a, b, dt,
-                       first);
+    hipLaunchKernelGGL((k_visc_apply<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, Qu, res, a, b, dt);
   return (int)hipGetLastError();
 }
 
