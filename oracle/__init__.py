@@ -32,6 +32,10 @@ Parity status per function (each pin lives in ``tests/test_oracle_*.py``):
                                  conservation, gradient convergence, symmetric
                                  negative heat-conduction operator, shear-wave
                                  rate convergence, independent 1-D BR1 code)
+  splitform.SplitFormDG          pinned (central two-point flux reproduces the
+                                 weak form of dg.DG, hand-worked Kennedy-Gruber
+                                 fixture, consistency and symmetry, free stream,
+                                 conservation, density-wave convergence)
 """
 
-from . import quadrature, euler, dg, lserk, viscous  # noqa: F401
+from . import quadrature, euler, dg, lserk, viscous, splitform  # noqa: F401

@@ -18,7 +18,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["test_oracle_quadrature.py", "test_oracle_euler.py", "test_oracle_dg.py", "test_oracle_lserk.py",
-             "test_oracle_adjoint.py", "test_oracle_viscous.py"]
+             "test_oracle_adjoint.py", "test_oracle_viscous.py", "test_oracle_splitform.py"]
 
 # (oracle file, exact text, replacement, what the mistake is)
 MUTATIONS = [
@@ -59,6 +59,16 @@ MUTATIONS = [
     ("viscous.py", "out = np.linalg.solve(self.M, (S - V)", "out = np.linalg.solve(self.M, (V - S)",
      "sign of the weak derivative"),
     ("viscous.py", "en = en + vel[k] * tau", "en = en", "viscous work dropped from the energy flux"),
+    ("splitform.py", "m = mass * (0.5 * (ua[k] + ub[k]))", "m = 0.5 * (qa[1 + k] + qb[1 + k]) * ud",
+     "momentum mean taken of rho u instead of the product of means"),
+    ("splitform.py", "out.append(mass * (0.5 * (ea + eb)) + pm * ud)", "out.append(mass * (0.5 * (ea + eb)))",
+     "pressure work dropped from the two-point energy flux"),
+    ("splitform.py", "Qn[N:, :N] = -0.5 * self.B1 @ self.E1", "Qn[N:, :N] = 0.5 * self.B1 @ self.E1",
+     "sign of the face-row coupling block"),
+    ("splitform.py", "r = r + np.einsum(\"fi,f,...f->...i\", self.E1, np.diag(self.B1), corr)",
+     "r = r - np.einsum(\"fi,f,...f->...i\", self.E1, np.diag(self.B1), corr)", "sign of the interface correction"),
+    ("splitform.py", "nbr_plus = np.roll(t_plus, 1, axis=ax)", "nbr_plus = np.roll(t_plus, -1, axis=ax)",
+     "wrong neighbour on the -d face"),
 ]
 
 
