@@ -37,6 +37,8 @@ WORKLOADS = {
                             "(one GPU's share at the paper's per-GPU size), 50 LSERK45 steps"),
     "tgv48_p4_re1600": (48, 4, 50, "viscous Taylor-Green vortex (Navier-Stokes, BR1 viscous terms), [0,2pi]^3, "
                                    "Mach 0.1, Re 1600 (mu = 1/1600, Pr 0.71), 48^3 elements, p=4, 50 LSERK45 steps"),
+    "tgv48_p4_kep": (48, 4, 50, "Taylor-Green vortex with the kinetic-energy-preserving split form (Kennedy-Gruber "
+                                "two-point flux), [0,2pi]^3, Mach 0.1, 48^3 elements, p=4, 50 LSERK45 steps"),
     "tgv40_p6": (40, 6, 100, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 40^3 elements, p=6 "
                              "(the paper's degree), 100 LSERK45 steps"),
     "adjoint16_p3": (16, 3, 40, "gradient of the integrated kinetic energy after 40 LSERK45 steps with respect to "
@@ -57,6 +59,8 @@ VISCOUS = {"tgv48_p4_re1600": (1.0 / 1600.0, 0.71)}
 # (read Q, write the flux) 136; k_visc_apply (read the flux, R, Q, res; write
 # Q, res) 296.
 VISC_BYTES = {"rhs": 80, "visc": 136 + 296}
+# Workloads on the split-form volume term (DG_VOLUME_KEP).
+SPLIT_FORM = {"tgv48_p4_kep"}
 
 
 def flops_per_dof_stage(N):
@@ -83,6 +87,7 @@ STAGE_SOURCES = {
                                                 "paper_2006_15698_amd/csrc/batch_api.cpp"],
     "vjp": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_vjp.hip"],
     "visc": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_visc.hip"],
+    "split": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_split.hip"],
 }
 
 
@@ -121,16 +126,18 @@ def measured_traffic(workload, family, options):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(n, p, L, budget_s, viscous=None):
+def cpu_baseline(n, p, L, budget_s, viscous=None, split=False):
     """The oracle (plain dense FP64 numpy) advancing RK stages of the same
     workload on the host for about ``budget_s`` seconds.  With viscosity
-    (mu, Pr) the Navier-Stokes oracle runs on a 16^3-element periodic block
-    of the same element size and degree (its cost per node is that of the
-    whole mesh; one stage of the full 48^3 mesh takes minutes)."""
+    (mu, Pr) the Navier-Stokes oracle, and for the split form the split-form
+    oracle, runs on a 16^3-element periodic block of the same element size
+    and degree (its cost per node is that of the whole mesh; one stage of
+    the full 48^3 mesh takes minutes)."""
     import numpy as np
     import workloads as W
     from oracle import lserk
     from oracle.dg import DG
+    from oracle.splitform import SplitFormDG
     from oracle.viscous import NavierStokesDG
     try:
         from threadpoolctl import threadpool_info
@@ -139,13 +146,16 @@ def cpu_baseline(n, p, L, budget_s, viscous=None):
     except Exception:
         threads = os.cpu_count()
     sample = ""
-    if viscous is None:
+    if viscous is None and not split:
         ora = DG((n, n, n), p, L=L)
         Q = W.tgv(n, p)
     else:
         m = min(n, 16)
         Lm = tuple(Ld * m / n for Ld in L)
-        ora = NavierStokesDG((m, m, m), p, L=Lm, mu=viscous[0], prandtl=viscous[1])
+        if split:
+            ora = SplitFormDG((m, m, m), p, L=Lm)
+        else:
+            ora = NavierStokesDG((m, m, m), p, L=Lm, mu=viscous[0], prandtl=viscous[1])
         Q = W.tgv(m, p, L=Lm)
         sample = f"a {m}^3-element block of the same element size and degree: "
     res = np.zeros_like(Q)
@@ -466,7 +476,9 @@ def main():
     prec = dg.DG_FP64 if args.precision == "fp64" else dg.DG_FP32_MFMA
     viscous = VISCOUS.get(args.workload)
     mu, prandtl = viscous if viscous else (0.0, 0.72)
-    s = dg.Solver((n, n, n), p, L=L, precision=prec, mu=mu, prandtl=prandtl)
+    split = args.workload in SPLIT_FORM
+    s = dg.Solver((n, n, n), p, L=L, precision=prec, mu=mu, prandtl=prandtl,
+                  volume_form=dg.DG_VOLUME_KEP if split else dg.DG_VOLUME_STANDARD)
     s.set_option(dg.DG_OPT_EXCHANGE, dg.DG_EXCHANGE_NEIGHBOUR if args.exchange == "neighbour"
                  else dg.DG_EXCHANGE_TRACES)
     for key, val in ((dg.DG_OPT_XCD_REMAP, args.xcd_remap),
@@ -557,6 +569,9 @@ def main():
         traffic = measured_traffic(args.workload, args.precision, s.options())
         kname = {("neighbour", "fp64"): "k_stage_nb", ("neighbour", "fp32"): "k_stage_nb32",
                  ("traces", "fp64"): "k_stage", ("traces", "fp32"): "k_stage32"}[(args.exchange, args.precision)]
+        if split:
+            kname = "k_split (split-form volume term, Kennedy-Gruber two-point flux)"
+            traffic = measured_traffic(args.workload, "split", s.options())
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "kernel": kname + " (fused RHS + LSERK45 stage, stages 2..5)",
@@ -570,11 +585,11 @@ def main():
                             "frac": fl / avg_s / 1e12 / FP64_PEAK_TFS,
                             "flops_per_dof_stage": flops_per_dof_stage(p + 1)}
 
-    if not args.no_precision_clause and not viscous:
+    if not args.no_precision_clause and not viscous and not split:
         out["fp32_mfma_vs_fp64"] = precision_clause(args, n, p, L, Q0, dt, K, Wm, graph, value)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, p, L, args.cpu_seconds, viscous)
+        out["cpu_baseline"] = cpu_baseline(n, p, L, args.cpu_seconds, viscous, split)
 
     print(json.dumps(out), flush=True)
 

@@ -110,6 +110,24 @@ int dg_set_precision(dg_ctx* ctx, int mode);
  * DG_EUNSUPPORTED.  DG_EINVAL for mu < 0, Pr <= 0 or non-finite values. */
 int dg_set_viscosity(dg_ctx* ctx, double mu, double prandtl);
 
+/* Volume term of the inviscid flux.  DG_VOLUME_STANDARD (default): the weak
+ * form of Eq. (5) with the volume integral of the flux at the collocated
+ * nodes.  DG_VOLUME_KEP: a kinetic-energy-preserving split form (the paper
+ * cites such flux schemes of its authors' framework, reference list, without
+ * printing one): flux differencing with Kennedy & Gruber's two-point flux
+ * ({rho}{u_d}, {rho}{u_d}{u_k} + {p} delta_kd, {rho}{u_d}{e} + {p}{u_d}, {.}
+ * the mean of two states, e = E / rho) along every d-line, whose
+ * Gauss-Legendre nodes are coupled with the two face traces by the
+ * hybridised summation-by-parts operator; the faces keep the local
+ * Lax-Friedrichs flux.  With the central two-point flux the form is the
+ * standard one.  The split form is FP64 only (DG_EUNSUPPORTED with
+ * DG_FP32_MFMA, in either order of the two calls); dg_rhs, dg_rk_stage,
+ * dg_rk_step(s), dg_rk_graph_steps (launching directly) and the viscous
+ * terms follow it; the adjoint calls and dg_rk_steps_noalloc return
+ * DG_EUNSUPPORTED while it is set. */
+enum { DG_VOLUME_STANDARD = 0, DG_VOLUME_KEP = 1 };
+int dg_set_volume_form(dg_ctx* ctx, int form);
+
 /* Tuning options (dg_set_option).
  * DG_OPT_EXCHANGE: how an FP64 stage obtains its neighbours' face traces.
  *   DG_EXCHANGE_NEIGHBOUR (default): interpolated in the launch itself from

@@ -208,11 +208,31 @@ int stages_nb(dg_ctx* c, double* Q, double* res, double dt, int s0, int count, d
   return DG_OK;
 }
 
-// Inviscid rate R = dQ/dt of the Euler terms by the neighbour-read kernel
-// (bitwise the same as the trace-buffer form).
+// Inviscid rate R = dQ/dt of the Euler terms: the split-form kernel, or the
+// neighbour-read kernel (bitwise the same as the trace-buffer form).
 int euler_rate_nb(dg_ctx* c, const double* Q, double* R) {
+  if (c->volume_form == DG_VOLUME_KEP) return dg_launch_split(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0);
   return c->precision == DG_FP32_MFMA ? dg_launch_stage_nb_f32(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0)
                                       : dg_launch_stage_nb(c, Q, nullptr, R, 0, 0.0, 0.0, 0.0, 0);
+}
+
+// Split-form stages: Q ping-pongs between Q and the workspace's second
+// state buffer like the neighbour-read stages (an odd count ends with a
+// copy back).
+int stages_split(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
+  double* buf[2] = {Q, q2_buf(c)};
+  for (int g = 0; g < count; ++g) {
+    const int s = (s0 + g) % 5;
+    int err = timed(c, s == 0 ? TK_STAGE_FIRST : TK_STAGE, [&] {
+      return dg_launch_split(c, buf[g & 1], buf[(g + 1) & 1], res, s == 0 ? 2 : 1, kRKA[s], kRKB[s], dt);
+    });
+    if (err) return hip_fail(err, "split-form stage launch");
+  }
+  if (count & 1) {
+    int err = (int)hipMemcpyAsync(Q, buf[1], state_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    if (err) return hip_fail(err, "state copy");
+  }
+  return DG_OK;
 }
 
 // Navier-Stokes stages: per stage the inviscid rate into the workspace, then
@@ -237,6 +257,7 @@ int stages(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
   // stage but the last writes the traces of its updated Q for the next.
   const bool f32 = c->precision == DG_FP32_MFMA;
   if (c->mu > 0.0) return stages_visc(c, Q, res, dt, s0, count);
+  if (c->volume_form == DG_VOLUME_KEP) return stages_split(c, Q, res, dt, s0, count);
   if (c->exchange == DG_EXCHANGE_NEIGHBOUR) return stages_nb(c, Q, res, dt, s0, count);
   int err = timed(c, TK_TRACE, [&] {
     return f32 ? dg_launch_trace_f32(c, Q, (char*)trace_buf(c, 0)) : dg_launch_trace(c, Q, trace_buf(c, 0));
@@ -443,6 +464,7 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
   c->mu = 0.0;
   c->prandtl = 0.72;
   c->kappa = 0.0;
+  c->volume_form = DG_VOLUME_STANDARD;
   c->epoch = 1;
   c->gstream = nullptr;
   c->ev_in = c->ev_out = nullptr;
@@ -525,6 +547,8 @@ int dg_set_precision(dg_ctx* c, int mode) {
   }
   if (mode == DG_FP32_MFMA) {
     if (!dg_f32_supported(c->N)) return fail(DG_EUNSUPPORTED, "FP32 matrix-core form not built for p=%d", c->p);
+    if (c->volume_form == DG_VOLUME_KEP)
+      return fail(DG_EUNSUPPORTED, "the split form runs in FP64 only (set DG_VOLUME_STANDARD first)");
     c->precision = mode;
     ++c->epoch;
     return DG_OK;
@@ -540,6 +564,16 @@ int dg_set_viscosity(dg_ctx* c, double mu, double prandtl) {
   c->mu = mu;
   c->prandtl = prandtl;
   c->kappa = mu * (c->gamma / (c->gamma - 1.0)) / prandtl;
+  ++c->epoch;
+  return DG_OK;
+}
+
+int dg_set_volume_form(dg_ctx* c, int form) {
+  if (!c) return fail(DG_EINVAL, "NULL context");
+  if (form != DG_VOLUME_STANDARD && form != DG_VOLUME_KEP) return fail(DG_EINVAL, "unknown volume form %d", form);
+  if (form == DG_VOLUME_KEP && c->precision == DG_FP32_MFMA)
+    return fail(DG_EUNSUPPORTED, "the split form runs in FP64 only (precision is the FP32 form)");
+  c->volume_form = form;
   ++c->epoch;
   return DG_OK;
 }
@@ -626,9 +660,10 @@ int dg_rhs(dg_ctx* c, const double* Q, double* R) {
   rc = check_state_pair(c, Q, "Q", R, "R");
   if (rc) return rc;
   const bool f32 = c->precision == DG_FP32_MFMA;
-  if (c->mu > 0.0) {
+  if (c->mu > 0.0 || c->volume_form == DG_VOLUME_KEP) {
     int err = timed(c, TK_RHS, [&] { return euler_rate_nb(c, Q, R); });
     if (err) return hip_fail(err, "rhs launch");
+    if (c->mu == 0.0) return DG_OK;
     double* Fv = (double*)(c->ws + dg_workspace_layout(c).off_visc_fv);
     err = timed(c, TK_VISC, [&] { return dg_launch_visc(c, Q, Fv, R, nullptr, nullptr, 0, 0.0, 0.0, 0.0, 0); });
     if (err) return hip_fail(err, "viscous rate launch");
@@ -684,6 +719,8 @@ int dg_rk_steps_noalloc(dg_ctx* c, double* Q, double* res, double dt, int nsteps
   int rc = check_state_pair(c, Q, "Q", res, "res");
   if (rc) return rc;
   if (c->mu > 0.0) return fail(DG_EUNSUPPORTED, "dg_rk_steps_noalloc covers the Euler terms only (viscosity is set)");
+  if (c->volume_form == DG_VOLUME_KEP)
+    return fail(DG_EUNSUPPORTED, "dg_rk_steps_noalloc covers the standard volume form only (the split form is set)");
   if (state_bytes(c) > kScratchBytes)
     return fail(DG_EUNSUPPORTED, "state of %zu bytes exceeds the %zu-byte static buffer of dg_rk_steps_noalloc",
                 state_bytes(c), kScratchBytes);
@@ -703,7 +740,8 @@ int dg_rk_graph_steps(dg_ctx* c, double* Q, double* res, double dt, int nsteps) 
   rc = check_state_pair(c, Q, "Q", res, "res");
   if (rc) return rc;
   if (nsteps == 0) return DG_OK;
-  if (c->exchange != DG_EXCHANGE_NEIGHBOUR || c->mu > 0.0) return stages(c, Q, res, dt, 0, 5 * nsteps);
+  if (c->exchange != DG_EXCHANGE_NEIGHBOUR || c->mu > 0.0 || c->volume_form == DG_VOLUME_KEP)
+    return stages(c, Q, res, dt, 0, 5 * nsteps);
   int err;
   if (!c->gstream) {
     err = (int)hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking);
@@ -775,6 +813,8 @@ int dg_rhs_vjp(dg_ctx* c, const double* Q, const double* gR, double* gQ) {
   int rc = check_ready(c);
   if (rc) return rc;
   if (c->mu > 0.0) return fail(DG_EUNSUPPORTED, "the adjoint covers the Euler terms only (viscosity is set)");
+  if (c->volume_form == DG_VOLUME_KEP)
+    return fail(DG_EUNSUPPORTED, "the adjoint covers the standard volume form only (the split form is set)");
   if (!Q || !gR || !gQ) return fail(DG_EINVAL, "NULL array");
   if (misaligned(Q) || misaligned(gR) || misaligned(gQ)) return fail(DG_EINVAL, "arrays must be 8-byte aligned");
   if (overlap(Q, gQ, state_bytes(c))) return fail(DG_EALIAS, "gQ overlaps Q");
@@ -788,6 +828,8 @@ int dg_rk_stage_vjp(dg_ctx* c, int s, const double* Qs, double* gQ, double* gres
   int rc = check_ready(c);
   if (rc) return rc;
   if (c->mu > 0.0) return fail(DG_EUNSUPPORTED, "the adjoint covers the Euler terms only (viscosity is set)");
+  if (c->volume_form == DG_VOLUME_KEP)
+    return fail(DG_EUNSUPPORTED, "the adjoint covers the standard volume form only (the split form is set)");
   if (s < 0 || s > 4) return fail(DG_EINVAL, "stage must be 0..4 (got %d)", s);
   if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
   if (!Qs || !gQ || !gres) return fail(DG_EINVAL, "NULL array");

@@ -55,6 +55,7 @@ struct dg_ctx {
   // viscous terms (dg_set_viscosity): dynamic viscosity, Prandtl number and
   // conductivity mu gamma / ((gamma - 1) Pr); mu = 0 is the Euler equations
   double mu, prandtl, kappa;
+  int volume_form;  // DG_VOLUME_STANDARD or DG_VOLUME_KEP (dg_set_volume_form)
   // graph replay of whole steps (dg_rk_graph_steps): one executable graph
   // per ping-pong parity, valid while the arrays, dt and `epoch` (bumped by
   // every setter that changes what a launch does) are unchanged
@@ -137,6 +138,12 @@ int dg_launch_vjp(const dg_ctx* c, const double* Q, const double* gR, double* gQ
 // and res with R the inviscid rate of the stage.
 int dg_launch_visc(const dg_ctx* c, const double* Q, double* Fv, double* R, double* Qu, double* res, int mode,
                    double a, double b, double dt, int first);
+
+// Kinetic-energy-preserving split form (kern_split.hip): mode 0 RR = dQ/dt;
+// mode 1 the LSERK45 stage Qin -> Qout with res = RR in place; mode 2 the
+// first stage.
+int dg_launch_split(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
+                    double dt);
 
 // Gradient of the kinetic-energy integral with respect to Q.
 int dg_launch_ke_grad(const dg_ctx* c, const double* Q, double* G);

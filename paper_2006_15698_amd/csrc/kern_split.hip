@@ -1,0 +1,252 @@
+// Kinetic-energy-preserving split-form volume term (flux differencing with
+// the Kennedy-Gruber two-point flux) on the collocated Gauss-Legendre basis.
+//
+// The paper cites kinetic-energy-preserving flux schemes of its authors' DG
+// framework (reference list) without printing one; the reading taken:
+//   two-point flux in direction d, {a} the mean of two states' values,
+//   e = E / rho:  {rho}{u_d},  {rho}{u_d}{u_k} + {p} delta_kd,
+//                 {rho}{u_d}{e} + {p}{u_d};
+//   the Gauss-Legendre nodes do not include the element ends, so each d-line
+//   couples its N nodes with the two face traces through the hybridised
+//   summation-by-parts operator; written out per node i of the line (mass
+//   matrix divided out, D_ia = l_a'(xi_i), l(+-1) the face interpolation
+//   weights):
+//     dQ_i/dt -= (2/h_d) [ sum_a 2 D_ia f_S(Q_i, Q_a)
+//                 + l_i(+1)/w_i B_+ - l_i(-1)/w_i B_- ],
+//     B_f = f_S(Q_i, Q~_f) - sum_a l_a(f) f_S(Q_i, Q_a)
+//           + F*_f - sum_a l_a(f) f_S(Q~_f, Q_a),
+//   Q~_f the element's own trace on face f, F*_f the local Lax-Friedrichs
+//   flux of the standard scheme there.  With the central two-point flux this
+//   is exactly the standard weak form.
+//
+// One workgroup per element, one thread per node (the pairwise fluxes make
+// the volume term O(N^4) per element, about 9N + 6 two-point fluxes per
+// node).  MODE 0: R = dQ/dt.  MODE 1: LSERK45 stage, Qout = Qin + b res
+// with res = a res + dt R in place (Qin and Qout differ: neighbours read
+// Qin).  MODE 2: the first stage (res = dt R without reading res).
+
+#include "dg_internal.h"
+#include "stage_fp64.h"
+
+namespace {
+
+template <int N>
+struct SCfg {
+  static constexpr int N2 = N * N;
+  static constexpr int N3 = N * N * N;
+  static constexpr int NT = N3 <= 64 ? 64 : (N3 + 63) / 64 * 64;
+};
+
+// Primitive description of a state: rho, u, v, w, p, e = E / rho.
+struct Prim {
+  double r, u[3], p, e;
+};
+
+__device__ __forceinline__ Prim to_prim(const double* q, double gm1) {
+  Prim s;
+  const double ri = dgdev::recip(q[0]);
+  s.r = q[0];
+  s.u[0] = q[1] * ri;
+  s.u[1] = q[2] * ri;
+  s.u[2] = q[3] * ri;
+  s.p = gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * ri);
+  s.e = q[4] * ri;
+  return s;
+}
+
+// Kennedy-Gruber two-point flux in direction D, accumulated with weight c.
+template <int D>
+__device__ __forceinline__ void kg_acc(const Prim& a, const Prim& b, double c, double* acc) {
+  const double rho = 0.5 * (a.r + b.r);
+  const double ud = 0.5 * (a.u[D] + b.u[D]);
+  const double pm = 0.5 * (a.p + b.p);
+  const double mass = rho * ud;
+  double f[5];
+  f[0] = mass;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[1 + k] = mass * (0.5 * (a.u[k] + b.u[k]));
+  f[1 + D] += pm;
+  f[4] = mass * (0.5 * (a.e + b.e)) + pm * ud;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) acc[v] = fma(c, f[v], acc[v]);
+}
+
+template <int N>
+__device__ __forceinline__ Prim lds_prim(const double (*P)[SCfg<N>::N3], int t) {
+  Prim s;
+  s.r = P[0][t];
+  s.u[0] = P[1][t];
+  s.u[1] = P[2][t];
+  s.u[2] = P[3][t];
+  s.p = P[4][t];
+  s.e = P[5][t];
+  return s;
+}
+
+template <int N>
+__device__ __forceinline__ Prim lds_tprim(const double (*T)[SCfg<N>::N2], int pt) {
+  Prim s;
+  s.r = T[0][pt];
+  s.u[0] = T[1][pt];
+  s.u[1] = T[2][pt];
+  s.u[2] = T[3][pt];
+  s.p = T[4][pt];
+  s.e = T[5][pt];
+  return s;
+}
+
+// Volume and face terms of direction D for node (m0 along the line, pt
+// across it) of the element whose node primitives are P, accumulated (with
+// the -(2/h_D) factor) into out.
+template <int N, int D>
+__device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)[SCfg<N>::N3],
+                                           const double (*Dm)[N], const double (*Tp)[6][SCfg<N>::N2],
+                                           const double (*Fs)[5][SCfg<N>::N2], int m0, int pt, double* out) {
+  const Prim si = lds_prim<N>(P, dgdev::tnode<N>(D, m0, pt));
+  double vol[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum_a 2 D_ia f_S(Q_i, Q_a)
+  double em[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(-1) f_S(Q_i, Q_a)
+  double ep[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(+1) f_S(Q_i, Q_a)
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const Prim sa = lds_prim<N>(P, dgdev::tnode<N>(D, a, pt));
+    double f[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    kg_acc<D>(si, sa, 1.0, f);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      vol[v] = fma(2.0 * Dm[m0][a], f[v], vol[v]);
+      em[v] = fma(tb.lm[a], f[v], em[v]);
+      ep[v] = fma(tb.lp[a], f[v], ep[v]);
+    }
+  }
+  double br[2][5];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const Prim tf = lds_tprim<N>(Tp[2 * D + s], pt);
+    double fi[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    kg_acc<D>(si, tf, 1.0, fi);                  // f_S(Q_i, Q~_f)
+    double sf[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(f) f_S(Q~_f, Q_a)
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const Prim sa = lds_prim<N>(P, dgdev::tnode<N>(D, a, pt));
+      kg_acc<D>(tf, sa, s ? tb.lp[a] : tb.lm[a], sf);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) br[s][v] = fi[v] - (s ? ep[v] : em[v]) + Fs[2 * D + s][v][pt] - sf[v];
+  }
+  const double sc = tb.sc[D];
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+    out[v] -= sc * (vol[v] + tb.liftp[m0] * br[1][v] - tb.liftm[m0] * br[0][v]);
+}
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(SCfg<N>::NT)
+k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR, double a,
+        double b, double dt) {
+  constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3, NT = SCfg<N>::NT;
+  __shared__ double P[6][N3];        // node primitives
+  __shared__ double Tp[6][6][N2];    // own trace primitives per face (2d + side)
+  __shared__ double Fs[6][5][N2];    // Lax-Friedrichs flux per face point
+  __shared__ double Dm[N][N];        // D_ia = l_a'(xi_i)
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const int64_t fs = (int64_t)tb.E * N3;
+  const double* qe = Qin + (int64_t)e * N3;
+  if (t < N2) {
+    const int i = t / N, aa = t % N;
+    // Dh[a N + i] = w_i l_a'(xi_i) / w_a
+    Dm[i][aa] = tb.Dh[aa * N + i] * tb.w[aa] / tb.w[i];
+  }
+  if (t < N3) {
+    double q[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) q[f] = qe[f * fs + t];
+    const Prim s = to_prim(q, tb.gm1);
+    P[0][t] = s.r;
+    P[1][t] = s.u[0];
+    P[2][t] = s.u[1];
+    P[3][t] = s.u[2];
+    P[4][t] = s.p;
+    P[5][t] = s.e;
+  }
+  for (int fp = t; fp < 6 * N2; fp += NT) {
+    const int face = fp / N2, pt = fp % N2, d = face >> 1, s = face & 1;
+    const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
+    const double* qn = Qin + (int64_t)en * N3;
+    double own[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, nbr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < N; ++m) {
+      const int node = dgdev::tnode<N>(d, m, pt);
+      const double wo = s ? tb.lp[m] : tb.lm[m];   // own trace on this face
+      const double wn = s ? tb.lm[m] : tb.lp[m];   // the neighbour's trace on its opposite face
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        own[f] = fma(wo, qe[f * fs + node], own[f]);
+        nbr[f] = fma(wn, qn[f * fs + node], nbr[f]);
+      }
+    }
+    double fl[5];
+    // the face's -d side state first
+    if (d == 0) s ? dgdev::lf_flux_d<0>(own, nbr, tb.gamma, tb.gm1, fl) : dgdev::lf_flux_d<0>(nbr, own, tb.gamma, tb.gm1, fl);
+    else if (d == 1) s ? dgdev::lf_flux_d<1>(own, nbr, tb.gamma, tb.gm1, fl) : dgdev::lf_flux_d<1>(nbr, own, tb.gamma, tb.gm1, fl);
+    else s ? dgdev::lf_flux_d<2>(own, nbr, tb.gamma, tb.gm1, fl) : dgdev::lf_flux_d<2>(nbr, own, tb.gamma, tb.gm1, fl);
+    const Prim so = to_prim(own, tb.gm1);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) Fs[face][f][pt] = fl[f];
+    Tp[face][0][pt] = so.r;
+    Tp[face][1][pt] = so.u[0];
+    Tp[face][2][pt] = so.u[1];
+    Tp[face][3][pt] = so.u[2];
+    Tp[face][4][pt] = so.p;
+    Tp[face][5][pt] = so.e;
+  }
+  __syncthreads();
+  if (t >= N3) return;
+  const int i = t % N, j = (t / N) % N, k = t / N2;
+  double rate[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  split_line<N, 0>(tb, P, Dm, Tp, Fs, i, j + N * k, rate);
+  split_line<N, 1>(tb, P, Dm, Tp, Fs, j, i + N * k, rate);
+  split_line<N, 2>(tb, P, Dm, Tp, Fs, k, i + N * j, rate);
+  const int64_t g = (int64_t)e * N3 + t;
+  if (MODE == 0) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) RR[f * fs + g] = rate[f];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const double r = MODE == 2 ? dt * rate[f] : fma(a, RR[f * fs + g], dt * rate[f]);
+      RR[f * fs + g] = r;
+      Qout[f * fs + g] = fma(b, r, Qin[f * fs + g]);
+    }
+  }
+}
+
+template <int N>
+int launch_split_n(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
+                   double dt) {
+  const unsigned grid = (unsigned)c->E;
+  const dim3 blk(SCfg<N>::NT);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_split<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt);
+  else if (mode == 2)
+    hipLaunchKernelGGL((k_split<N, 2>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt);
+  else
+    hipLaunchKernelGGL((k_split<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt);
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int dg_launch_split(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
+                    double dt) {
+  switch (c->N) {
+    case 1: return launch_split_n<1>(c, Qin, Qout, RR, mode, a, b, dt);
+    case 2: return launch_split_n<2>(c, Qin, Qout, RR, mode, a, b, dt);
+    case 3: return launch_split_n<3>(c, Qin, Qout, RR, mode, a, b, dt);
+    case 4: return launch_split_n<4>(c, Qin, Qout, RR, mode, a, b, dt);
+    case 5: return launch_split_n<5>(c, Qin, Qout, RR, mode, a, b, dt);
+    case 6: return launch_split_n<6>(c, Qin, Qout, RR, mode, a, b, dt);
+    case 7: return launch_split_n<7>(c, Qin, Qout, RR, mode, a, b, dt);
+    case 8: return launch_split_n<8>(c, Qin, Qout, RR, mode, a, b, dt);
+    default: return (int)hipErrorInvalidValue;
+  }
+}

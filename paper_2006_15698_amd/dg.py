@@ -36,6 +36,8 @@ DG_ENONPHYSICAL = -5
 DG_EWORKSPACE = -6
 DG_FP64 = 0
 DG_FP32_MFMA = 1
+DG_VOLUME_STANDARD = 0
+DG_VOLUME_KEP = 1
 DG_OPT_EXCHANGE = 1
 DG_OPT_XCD_REMAP = 2
 DG_OPT_ORDER = 3
@@ -63,6 +65,7 @@ _SIGS = {
     "dg_set_stream": (_i, [_vp, _vp]),
     "dg_set_precision": (_i, [_vp, _i]),
     "dg_set_viscosity": (_i, [_vp, _d, _d]),
+    "dg_set_volume_form": (_i, [_vp, _i]),
     "dg_workspace_bytes": (_sz, [_vp]),
     "dg_set_workspace": (_i, [_vp, _vp, _sz]),
     "dg_num_dof": (_i64, [_vp]),
@@ -179,6 +182,10 @@ def dg_set_precision(ctx, mode):
 
 def dg_set_viscosity(ctx, mu, prandtl=0.72):
     return _check(_lib.dg_set_viscosity(ctx, float(mu), float(prandtl)))
+
+
+def dg_set_volume_form(ctx, form):
+    return _check(_lib.dg_set_volume_form(ctx, int(form)))
 
 
 def dg_set_option(ctx, key, value):
@@ -470,7 +477,8 @@ class Solver:
     """One periodic mesh on one GPU: owns the context and a torch-allocated
     workspace, and enqueues every call on the current torch stream."""
 
-    def __init__(self, n, p, L=(1.0, 1.0, 1.0), gamma=1.4, precision=DG_FP64, device=None, mu=0.0, prandtl=0.72):
+    def __init__(self, n, p, L=(1.0, 1.0, 1.0), gamma=1.4, precision=DG_FP64, device=None, mu=0.0, prandtl=0.72,
+                 volume_form=DG_VOLUME_STANDARD):
         import torch
         if isinstance(n, int):
             n = (n, n, n)
@@ -483,6 +491,7 @@ class Solver:
         self.ctx = dg_create(*self.n, self.p, self.gamma)
         dg_set_domain(self.ctx, *self.L)
         dg_set_precision(self.ctx, precision)
+        dg_set_volume_form(self.ctx, volume_form)
         self.mu, self.prandtl = float(mu), float(prandtl)
         dg_set_viscosity(self.ctx, self.mu, self.prandtl)
         self.workspace = None

@@ -37,14 +37,14 @@ def rhs_errors(dg, Q, R_gpu, R_ora):
     return plain, scaled
 
 
-def patch_rhs(n, p, L, Q, elems, gamma=1.4):
+def patch_rhs(n, p, L, Q, elems, gamma=1.4, make=DG):
     """Oracle right-hand side at selected elements of a large periodic mesh.
     The RHS of an element depends only on it and its six face neighbours, so
     it equals the RHS of the centre element of the 3x3x3 periodic patch
     around it (same element size).  Returns {(ex,ey,ez): R[5,N,N,N]}."""
     nx, ny, nz = n
     h = np.array(L, dtype=np.float64) / np.array(n)
-    small = DG((3, 3, 3), p, L=tuple(3 * h), gamma=gamma)
+    small = make((3, 3, 3), p, L=tuple(3 * h), gamma=gamma)
     out = {}
     for (ex, ey, ez) in elems:
         xs = [(ex + o) % nx for o in (-1, 0, 1)]
@@ -100,3 +100,20 @@ def patch_rhs_viscous(n, p, L, Q, elems, mu, prandtl, gamma=1.4):
         R = small.rhs(np.ascontiguousarray(patch))
         out[(ex, ey, ez)] = R[:, 2, 2, 2]
     return out
+
+
+def split_summand_scale(dg, Q):
+    """Per field: the summand scale of the split-form rate, the inviscid one
+    with the larger of max_i sum_a |D_ia| and max_i sum_a |w_a D_ai / w_i|
+    (both line operators appear) and a factor 2 for the two-point sums."""
+    q = np.asarray(Q).reshape(5, -1)
+    xi, w = gauss_legendre(dg.N)
+    dh = 1.0
+    if dg.N > 1:
+        D = lagrange_deriv(xi, xi)
+        dh = max(1.0, float(np.max(np.sum(np.abs(w[:, None] * D / w[None, :]), axis=0))),
+                 float(np.max(np.sum(np.abs(D), axis=1))))
+    s = np.zeros_like(q)
+    for d in range(3):
+        s = s + (2.0 / dg.h[d]) * np.abs(flux(q, d, dg.gamma))
+    return 2.0 * np.max(s, axis=1) * dh
