@@ -96,19 +96,36 @@ void build_items(dg_batch* b) {
               cost.push_back(std::min(epb, nx - x0) * N3);
             }
   }
-  // XCD split by node count
-  int64_t total = 0;
-  for (int64_t c : cost) total += c;
+  // XCD split: every degree group (contiguous in the list) is cut into 8
+  // contiguous parts of equal node count, and XCD x gets part x of every
+  // group, so each XCD runs the same mix of degrees (equal node counts of one
+  // degree are equal work) on neighbouring items
   b->split.xcd = b->xcd;
-  b->split.bounds[0] = 0;
-  int64_t acc = 0;
-  size_t k = 0;
-  for (int x = 1; x < 8; ++x) {
-    const int64_t target = total * x / 8;
-    while (k < cost.size() && acc < target) acc += cost[k++];
-    b->split.bounds[x] = (int)k;
+  if (b->xcd) {
+    std::vector<int2> out;
+    out.reserve(b->items.size());
+    std::vector<size_t> group = {0};
+    for (size_t k = 1; k < b->items.size(); ++k)
+      if (b->inst[b->items[k].x].N != b->inst[b->items[k - 1].x].N) group.push_back(k);
+    group.push_back(b->items.size());
+    for (int x = 0; x < 8; ++x) {
+      b->split.bounds[x] = (int)out.size();
+      for (size_t gi = 0; gi + 1 < group.size(); ++gi) {
+        int64_t total = 0;
+        for (size_t k = group[gi]; k < group[gi + 1]; ++k) total += cost[k];
+        const int64_t lo = total * x / 8, hi = total * (x + 1) / 8;
+        int64_t acc = 0;   // node count before item k within the group
+        for (size_t k = group[gi]; k < group[gi + 1]; ++k) {
+          if (acc >= lo && acc < hi) out.push_back(b->items[k]);
+          acc += cost[k];
+        }
+      }
+    }
+    b->split.bounds[8] = (int)out.size();
+    b->items.swap(out);
+  } else {
+    for (int x = 0; x <= 8; ++x) b->split.bounds[x] = x == 8 ? (int)b->items.size() : 0;
   }
-  b->split.bounds[8] = (int)b->items.size();
   b->uploaded = false;
 }
 
