@@ -318,10 +318,12 @@ int dg_batch_set_precision(dg_batch* b, int mode);
 int dg_batch_set_tile(dg_batch* b, int p, int epb);
 /* Order in which the persistent launch walks the work list; the results are
  * bitwise the same for every setting.  Keys as for dg_set_option:
- * DG_OPT_XCD_REMAP 1 cuts the work list into 8 contiguous parts of about
- *   equal node count, one per XCD of the MI355X, so that the items that run
- *   at the same time on one XCD are neighbours in the list and share its
- *   L2; 0 (default) deals every item to the whole grid round robin.
+ * DG_OPT_XCD_REMAP 1 cuts every degree group of the work list into 8
+ *   contiguous parts of equal node count and gives part x of each group to
+ *   XCD x of the MI355X, so that every XCD runs the same mix of degrees and
+ *   the items that run at the same time on one XCD are neighbours in the
+ *   list and share its L2; 0 (default) deals every item to the whole grid
+ *   round robin.
  * DG_OPT_ORDER: items of a mesh row by row (DG_ORDER_LINEAR, default) or in
  *   pencils of DG_OPT_PENCIL_X elements (0 = the whole row) by
  *   DG_OPT_PENCIL_Z planes swept along y (DG_ORDER_PENCIL; 16 x 8 when

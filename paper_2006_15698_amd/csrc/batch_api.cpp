@@ -37,8 +37,9 @@ struct dg_batch {
   int gprec = -1;
   unsigned grid[2] = {0, 0};   // persistent grid per precision (FP64, FP32 form)
   // visiting order of the work list (dg_batch_set_option)
-  // defaults: the fastest measured on the 512-mesh workload (the XCD split
-  // was 10% slower in FP64 and 18% in the FP32 form, pencils within 1%)
+  // defaults: the measured rates on the 512-mesh workload are within 1.5%
+  // of each other for every setting (the XCD split +1.5% in FP64, -1% in
+  // the FP32 form; pencils within 1%)
   int xcd = 0;                 // each XCD walks its own contiguous part of the list
   int order = DG_ORDER_LINEAR; // item order within a mesh
   int pencil_x = 16;           // elements of a pencil along x (0 = whole row)
@@ -69,7 +70,7 @@ Layout layout(const dg_batch* b) {
 // consecutive elements of one x-row, visited row by row (DG_ORDER_LINEAR) or
 // in pencils of pencil_x elements by pencil_z planes swept along y
 // (DG_ORDER_PENCIL), so that an item's y- and z-neighbours are listed close
-// to it.  Then the XCD split: 8 contiguous parts of about equal node count.
+// to it.  Then, when the XCD split is on, the degree-mixed split below.
 void build_items(dg_batch* b) {
   b->items.clear();
   std::vector<int> order(b->count);
