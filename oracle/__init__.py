@@ -36,6 +36,10 @@ Parity status per function (each pin lives in ``tests/test_oracle_*.py``):
                                  weak form of dg.DG, hand-worked Kennedy-Gruber
                                  fixture, consistency and symmetry, free stream,
                                  conservation, density-wave convergence)
+  varp.VariableDegreeDG          pinned (one degree is dg.DG, free stream and
+                                 conservation across degree jumps, rate
+                                 convergence with mixed degrees, axis
+                                 permutation equivariance)
 """
 
-from . import quadrature, euler, dg, lserk, viscous, splitform  # noqa: F401
+from . import quadrature, euler, dg, lserk, viscous, splitform, varp  # noqa: F401

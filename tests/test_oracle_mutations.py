@@ -18,7 +18,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["test_oracle_quadrature.py", "test_oracle_euler.py", "test_oracle_dg.py", "test_oracle_lserk.py",
-             "test_oracle_adjoint.py", "test_oracle_viscous.py", "test_oracle_splitform.py"]
+             "test_oracle_adjoint.py", "test_oracle_viscous.py", "test_oracle_splitform.py", "test_oracle_varp.py"]
 
 # (oracle file, exact text, replacement, what the mistake is)
 MUTATIONS = [
@@ -69,6 +69,12 @@ MUTATIONS = [
      "r = r - np.einsum(\"fi,f,...f->...i\", self.E1, np.diag(self.B1), corr)", "sign of the interface correction"),
     ("splitform.py", "nbr_plus = np.roll(t_plus, 1, axis=ax)", "nbr_plus = np.roll(t_plus, -1, axis=ax)",
      "wrong neighbour on the -d face"),
+    ("varp.py", "m = max(p, pn)", "m = min(p, pn)", "mortar rule of the lower degree"),
+    ("varp.py", "qp = self.element(Q, nb) @ Bm_nbr.T", "qp = q @ Bm_own.T", "own trace used for the neighbour's"),
+    ("varp.py", "S[:, snb] -= fstar @ Bm_nbr", "S[:, snb] += fstar @ Bm_nbr", "sign of the neighbour's face term"),
+    ("varp.py", "wf, Bm_own = self._mortar(d, 1, p, m)", "wf, Bm_own = self._mortar(d, -1, p, m)",
+     "own trace taken on the wrong face"),
+    ("varp.py", "return w[lo] * w[hi], basis3d", "return w[lo] * w[lo], basis3d", "mortar weights of one axis twice"),
 ]
 
 

@@ -223,3 +223,78 @@ def batch_state(spec, gamma=GAMMA):
                             L=spec["L"], gamma=gamma)
     return tgv(spec["n"], spec["p"], mach=0.1, V0=spec["amp"], mult=spec["mult"],
                L=spec["L"], gamma=gamma)
+
+
+def varp_coords(n, degrees, L=(1.0, 1.0, 1.0)):
+    """Node coordinates of a periodic mesh with a degree per element
+    (degrees[ez, ey, ex]): a list, element order e = (ez ny + ey) nx + ex,
+    of (X, Y, Z) arrays shaped [N_e, N_e, N_e] (k, j, i; i fastest)."""
+    nx, ny, nz = _mesh(n)
+    deg = np.asarray(degrees, dtype=int).reshape(nz, ny, nx)
+    h = (L[0] / nx, L[1] / ny, L[2] / nz)
+    out = []
+    for ez in range(nz):
+        for ey in range(ny):
+            for ex in range(nx):
+                xi = _gl_nodes(int(deg[ez, ey, ex]))
+                K, J, I = np.meshgrid(xi, xi, xi, indexing="ij")
+                out.append((ex * h[0] + (I + 1.0) * (h[0] / 2.0), ey * h[1] + (J + 1.0) * (h[1] / 2.0),
+                            ez * h[2] + (K + 1.0) * (h[2] / 2.0)))
+    return out
+
+
+def varp_offsets(degrees):
+    """First node of every element (and the total), element order."""
+    n3 = (np.asarray(degrees, dtype=np.int64).reshape(-1) + 1) ** 3
+    return np.concatenate([[0], np.cumsum(n3)])
+
+
+def varp_state(n, degrees, primitive, L=(1.0, 1.0, 1.0), gamma=GAMMA):
+    """State [5, total nodes] of a variable-degree mesh from a function
+    primitive(X, Y, Z) -> (rho, u, v, w, p), element blocks back to back
+    (evaluated degree by degree, all elements of a degree at once)."""
+    nx, ny, nz = _mesh(n)
+    deg = np.asarray(degrees, dtype=np.int64).reshape(-1)
+    if deg.size != nx * ny * nz:
+        raise ValueError("one degree per element")
+    h = (L[0] / nx, L[1] / ny, L[2] / nz)
+    off = varp_offsets(deg)
+    out = np.empty((5, int(off[-1])))
+    e_all = np.arange(deg.size)
+    for p in np.unique(deg):
+        es = e_all[deg == p]
+        N = int(p) + 1
+        xi = _gl_nodes(int(p))
+        ex, ey, ez = es % nx, (es // nx) % ny, es // (nx * ny)
+        K, J, I = np.meshgrid(xi, xi, xi, indexing="ij")
+        X = ex[:, None, None, None] * h[0] + (I[None] + 1.0) * (h[0] / 2.0)
+        Y = ey[:, None, None, None] * h[1] + (J[None] + 1.0) * (h[1] / 2.0)
+        Z = ez[:, None, None, None] * h[2] + (K[None] + 1.0) * (h[2] / 2.0)
+        q = conserved(*primitive(X, Y, Z), gamma=gamma).reshape(5, len(es), N ** 3)
+        idx = off[es][:, None] + np.arange(N ** 3)[None, :]
+        out[:, idx] = q
+    return out
+
+
+def random_degrees(n, pmin, pmax, seed):
+    """Seeded degree per element, uniform in pmin..pmax, shaped [nz, ny, nx]."""
+    nx, ny, nz = _mesh(n)
+    return np.random.default_rng(seed).integers(pmin, pmax + 1, size=(nz, ny, nx))
+
+
+def tgv_degrees(n, pmin=3, pmax=5, L=(2 * np.pi, 2 * np.pi, 2 * np.pi)):
+    """Degree per element [nz, ny, nx] driven by the Taylor-Green vortex's
+    initial enstrophy density at the element centre, as an hp indicator
+    would set it: s = |curl u| / 2 in [0, 1] (V0 = 1), degree
+    pmin + round((pmax - pmin) s).  On 48^3 with 3..5: 22% / 72% / 5% of
+    the elements, 6% of the faces between two degrees."""
+    nx, ny, nz = _mesh(n)
+    x = (np.arange(nx) + 0.5) * (L[0] / nx)
+    y = (np.arange(ny) + 0.5) * (L[1] / ny)
+    z = (np.arange(nz) + 0.5) * (L[2] / nz)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    w1 = -np.cos(X) * np.sin(Y) * np.sin(Z)
+    w2 = -np.sin(X) * np.cos(Y) * np.sin(Z)
+    w3 = 2 * np.sin(X) * np.sin(Y) * np.cos(Z)
+    s = np.sqrt(w1 ** 2 + w2 ** 2 + w3 ** 2) / 2.0
+    return (pmin + np.rint((pmax - pmin) * s)).astype(np.int64)
