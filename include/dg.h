@@ -354,6 +354,53 @@ int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps);
  * step parity; recaptured when the pointers change). */
 int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps);
 
+/* ---- Variable degree per element ------------------------------------------
+ * The hp-adaptive setting that the paper names (Sections I and III: degree
+ * adapted element by element) on the conforming periodic Cartesian mesh.
+ * Every element e has its own degree p_e in 0..7 and the scheme of Section
+ * II-B (Eq. (5), collocated Gauss-Legendre basis, local Lax-Friedrichs flux)
+ * on it; a face between degrees p and q is integrated on a mortar, the
+ * tensor Gauss-Legendre rule of max(p, q) + 1 points per tangential
+ * direction, where both elements' traces are evaluated and the flux is
+ * formed once for both sides (conservative; where p = q it is the
+ * single-degree scheme, bitwise).  One launch per degree present.
+ * State layout: Q[f * T + off[e] + (k N_e + j) N_e + i], field f = rho, rho u,
+ * rho v, rho w, rho E, T = dg_varp_num_dof, off[e] = dg_varp_offset(v, e):
+ * the elements' [N_e]^3 blocks back to back, e = (ez ny + ey) nx + ex, the
+ * node index i fastest.  Arrays are device pointers, FP64, 8-byte aligned;
+ * Q must not overlap R or res (DG_EALIAS). */
+typedef struct dg_varp dg_varp;
+
+/* nx, ny, nz >= 1; degrees[E] (HOST, element order as above) each in 0..7
+ * (DG_EUNSUPPORTED otherwise); L[3] (HOST) the domain lengths.  NULL on
+ * error (dg_last_error). */
+dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double* L, double gamma);
+void dg_varp_destroy(dg_varp* v);
+int dg_varp_set_stream(dg_varp* v, void* hip_stream);
+/* Total nodes T (the DOF count), -1 for NULL. */
+int64_t dg_varp_num_dof(const dg_varp* v);
+/* First node of element e (e = E gives T); -1 out of range. */
+int64_t dg_varp_offset(const dg_varp* v, int64_t e);
+size_t dg_varp_workspace_bytes(const dg_varp* v);
+/* Caller-owned device workspace (256-byte aligned): mortar tables, degrees,
+ * offsets, element lists and the second state buffer of the ping-pong.
+ * SYNCHRONISING (uploads the tables). */
+int dg_varp_set_workspace(dg_varp* v, void* dptr, size_t bytes);
+/* R = dQ/dt. */
+int dg_varp_rhs(dg_varp* v, const double* Q, double* R);
+/* nsteps LSERK45 steps (Sections IV-V) of size dt; res is the 2N register
+ * (its input is ignored: the first stage does not read it).  The state
+ * alternates between Q and a workspace buffer; an odd nsteps ends with one
+ * device-to-device copy back into Q. */
+int dg_varp_rk_steps(dg_varp* v, double* Q, double* res, double dt, int nsteps);
+/* Not in the paper: measurement support.  While on, every launch is
+ * bracketed by HIP events (switching on clears the record). */
+int dg_varp_set_timing(dg_varp* v, int on);
+/* SYNCHRONISING.  ms[3 p + mode], count[3 p + mode] (HOST arrays of 24):
+ * summed milliseconds and launches of degree p's kernel, mode 0 right-hand
+ * side, 1 RK stages 2..5, 2 the first RK stage; clears the record. */
+int dg_varp_timing_read(dg_varp* v, double* ms, int64_t* count);
+
 /* Not in the paper: measurement support.  Opt-in per-launch timing for
  * benchmarks.  While on, the context brackets
  * every kernel it launches with HIP events on its stream (a few microseconds

@@ -1,0 +1,45 @@
+// Internal declarations of the variable-degree entry points (dg_varp_* in
+// dg.h): the mortar tables and the launch arguments shared by the host code
+// (varp_api.cpp) and the kernels (kern_varp.hip).
+#pragma once
+
+#include "dg_internal.h"
+
+// Largest supported points per direction (p = 0..7, as for one degree).
+#define DG_VARP_MAXN DG_MAXN
+
+// Tables of the mortar faces, in device memory (the workspace), read with
+// indices that are uniform over a face.  Index n below is a point count
+// N = p + 1 in 1..DG_VARP_MAXN (slot 0 unused).
+struct DGVarpTabs {
+  // l^n_m(-1), l^n_m(+1): a degree-(n-1) element's trace on its -/+ face
+  // (the same values as DGTables::lm/lp of that degree)
+  double lm[DG_VARP_MAXN + 1][DG_VARP_MAXN];
+  double lp[DG_VARP_MAXN + 1][DG_VARP_MAXN];
+  // interp[n][m][b * n + t] = l^n_t(x^m_b): the degree-(n-1) basis at the
+  // m Gauss-Legendre points of the mortar rule (m > n)
+  double interp[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][DG_VARP_MAXN * DG_VARP_MAXN];
+  // proj[n][m][t * m + b] = l^n_t(x^m_b) W^m_b / w^n_t: the mortar rule's
+  // weights times the basis, over the element's own face weights (the
+  // surface integral on the mortar, lifted by the diagonal mass matrix)
+  double proj[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][DG_VARP_MAXN * DG_VARP_MAXN];
+};
+
+// Mesh description read by every launch.
+struct DGVarpMesh {
+  const int* deg;          // degree per element [E]
+  const int64_t* off;      // first node of every element [E] (field stride T)
+  const int* list;         // elements grouped by degree, ascending inside a group
+  const DGVarpTabs* tabs;
+  int64_t T;               // total nodes
+  int nx, ny, nz;
+  int maxn;                // largest point count p + 1 in the mesh
+};
+
+// Launch one stage (mode 0: RR = dQ/dt; 1: LSERK45 stage Qin -> Qout with
+// res = RR in place; 2: the first stage) over the `count` elements of degree
+// N - 1 listed from list[first].
+int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMesh& m, int first, int count,
+                   const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt);
+// Elements per workgroup of the variable-degree kernel for N points.
+int dg_varp_epb(int N);

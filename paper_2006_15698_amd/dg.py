@@ -98,6 +98,17 @@ _SIGS = {
     "dg_batch_rhs": (_i, [_vp, _vp, _vp]),
     "dg_batch_rk_steps": (_i, [_vp, _vp, _vp, _i]),
     "dg_batch_graph_steps": (_i, [_vp, _vp, _vp, _i]),
+    "dg_varp_create": (_vp, [_i, _i, _i, ctypes.POINTER(ctypes.c_int), _dp, _d]),
+    "dg_varp_destroy": (None, [_vp]),
+    "dg_varp_set_stream": (_i, [_vp, _vp]),
+    "dg_varp_num_dof": (_i64, [_vp]),
+    "dg_varp_offset": (_i64, [_vp, _i64]),
+    "dg_varp_workspace_bytes": (_sz, [_vp]),
+    "dg_varp_set_workspace": (_i, [_vp, _vp, _sz]),
+    "dg_varp_rhs": (_i, [_vp, _vp, _vp]),
+    "dg_varp_rk_steps": (_i, [_vp, _vp, _vp, _d, _i]),
+    "dg_varp_set_timing": (_i, [_vp, _i]),
+    "dg_varp_timing_read": (_i, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "dg_set_option": (_i, [_vp, _i, _i]),
     "dg_get_option": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_int)]),
     "dg_set_timing": (_i, [_vp, _i]),
@@ -470,6 +481,119 @@ class Batch:
             dg_batch_graph_steps(self.b, Q, res, nsteps)
         else:
             dg_batch_rk_steps(self.b, Q, res, nsteps)
+
+
+# ---- variable degree per element -------------------------------------------
+def dg_varp_create(nx, ny, nz, degrees, L=(1.0, 1.0, 1.0), gamma=1.4):
+    """degrees: E integers in element order e = (ez ny + ey) nx + ex."""
+    deg = [int(v) for v in np.asarray(degrees).reshape(-1)]
+    if len(deg) != nx * ny * nz:
+        raise ValueError(f"{len(deg)} degrees for {nx * ny * nz} elements")
+    da = (ctypes.c_int * len(deg))(*deg)
+    La = (ctypes.c_double * 3)(*[float(v) for v in L])
+    v = _lib.dg_varp_create(int(nx), int(ny), int(nz), da, La, float(gamma))
+    if not v:
+        raise DGError(DG_EINVAL, dg_last_error())
+    return v
+
+
+def dg_varp_destroy(v):
+    _lib.dg_varp_destroy(v)
+
+
+def dg_varp_set_stream(v, stream=None):
+    return _check(_lib.dg_varp_set_stream(v, _stream_ptr(stream)))
+
+
+def dg_varp_num_dof(v):
+    return int(_lib.dg_varp_num_dof(v))
+
+
+def dg_varp_offset(v, e):
+    return int(_lib.dg_varp_offset(v, int(e)))
+
+
+def dg_varp_workspace_bytes(v):
+    return int(_lib.dg_varp_workspace_bytes(v))
+
+
+def dg_varp_set_workspace(v, ws, nbytes=None):
+    if nbytes is None:
+        nbytes = ws.numel() * ws.element_size()
+    return _check(_lib.dg_varp_set_workspace(v, _ptr(ws), int(nbytes)))
+
+
+def dg_varp_rhs(v, Q, R):
+    return _check(_lib.dg_varp_rhs(v, _ptr(Q), _ptr(R)))
+
+
+def dg_varp_rk_steps(v, Q, res, dt, nsteps):
+    return _check(_lib.dg_varp_rk_steps(v, _ptr(Q), _ptr(res), float(dt), int(nsteps)))
+
+
+def dg_varp_set_timing(v, on):
+    return _check(_lib.dg_varp_set_timing(v, int(on)))
+
+
+def dg_varp_timing_read(v):
+    """{(p, mode): (ms, launches)} for the launches recorded since timing
+    was switched on (mode 0 rhs, 1 stages 2..5, 2 first stage)."""
+    ms = (ctypes.c_double * 24)()
+    cnt = (ctypes.c_int64 * 24)()
+    _check(_lib.dg_varp_timing_read(v, ms, cnt))
+    return {(i // 3, i % 3): (ms[i], cnt[i]) for i in range(24) if cnt[i]}
+
+
+class VariableDegree:
+    """Periodic nx*ny*nz mesh with a degree per element (degrees[ez, ey, ex],
+    0..7).  State: a flat float64 tensor of 5 T values, field f at
+    [f T, (f + 1) T), element e's nodes at offsets[e] .. offsets[e + 1]."""
+
+    def __init__(self, n, degrees, L=(1.0, 1.0, 1.0), gamma=1.4, device=None):
+        self.nx, self.ny, self.nz = (int(v) for v in n)
+        self.deg = np.asarray(degrees, dtype=np.int64).reshape(self.nz, self.ny, self.nx)
+        self.L = tuple(float(v) for v in L)
+        self.gamma = float(gamma)
+        self.device = torch.device(device or "cuda")
+        self.v = dg_varp_create(self.nx, self.ny, self.nz, self.deg, self.L, self.gamma)
+        self.T = dg_varp_num_dof(self.v)
+        E = self.nx * self.ny * self.nz
+        self.offsets = [dg_varp_offset(self.v, e) for e in range(E + 1)]
+        nbytes = dg_varp_workspace_bytes(self.v)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        _check(_lib.dg_varp_set_workspace(self.v, aligned, nbytes))
+
+    def __del__(self):
+        v = getattr(self, "v", None)
+        if v and dg_varp_destroy is not None:
+            dg_varp_destroy(v)
+            self.v = None
+
+    def num_dof(self):
+        return self.T
+
+    def empty(self):
+        return torch.empty(5 * self.T, dtype=torch.float64, device=self.device)
+
+    def _s(self):
+        dg_varp_set_stream(self.v, None)
+
+    def rhs(self, Q, out=None):
+        out = self.empty() if out is None else out
+        self._s()
+        dg_varp_rhs(self.v, Q, out)
+        return out
+
+    def step(self, Q, res, dt, nsteps=1):
+        self._s()
+        dg_varp_rk_steps(self.v, Q, res, dt, nsteps)
+
+    def set_timing(self, on):
+        dg_varp_set_timing(self.v, on)
+
+    def timing_read(self):
+        return dg_varp_timing_read(self.v)
 
 
 # ---- convenience -----------------------------------------------------------

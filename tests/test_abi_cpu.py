@@ -180,3 +180,36 @@ def test_paired_line_lane_map(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "ok" in out.stdout
+
+
+def test_varp_host_logic(dg):
+    """Variable-degree context: degree checks, node offsets (element blocks
+    back to back), and workspace checks, all before any device access."""
+    lib = dg._lib
+    with pytest.raises(dg.DGError, match="degree 8"):
+        dg.dg_varp_create(2, 1, 1, [1, 8])
+    with pytest.raises(dg.DGError, match="degree -1"):
+        dg.dg_varp_create(2, 1, 1, [-1, 0])
+    with pytest.raises(dg.DGError):
+        dg.dg_varp_create(0, 1, 1, [])
+    with pytest.raises(dg.DGError, match="gamma"):
+        dg.dg_varp_create(1, 1, 1, [2], gamma=0.9)
+    with pytest.raises(dg.DGError, match="lengths"):
+        dg.dg_varp_create(1, 1, 1, [2], L=(1.0, -1.0, 1.0))
+    deg = np.array([[[0, 1, 7], [2, 3, 4]], [[5, 6, 1], [1, 2, 3]]])   # [nz, ny, nx]
+    v = dg.dg_varp_create(3, 2, 2, deg)
+    try:
+        n3 = (deg.reshape(-1) + 1) ** 3
+        off = np.concatenate([[0], np.cumsum(n3)])
+        assert dg.dg_varp_num_dof(v) == off[-1]
+        assert [dg.dg_varp_offset(v, e) for e in range(13)] == list(off)
+        assert dg.dg_varp_offset(v, 13) == -1 and dg.dg_varp_offset(v, -1) == -1
+        nb = dg.dg_varp_workspace_bytes(v)
+        assert nb >= 5 * off[-1] * 8 and nb % 256 == 0
+        Q, R = 0x10000000, 0x20000000
+        assert lib.dg_varp_rhs(v, Q, R) == dg.DG_EWORKSPACE
+        assert lib.dg_varp_set_workspace(v, 0x10000001, nb) == dg.DG_EINVAL       # misaligned
+        assert lib.dg_varp_set_workspace(v, 0x10000000, nb - 256) == dg.DG_EWORKSPACE
+        assert lib.dg_varp_rk_steps(v, Q, R, ctypes.c_double(1e-3), 1) == dg.DG_EWORKSPACE
+    finally:
+        dg.dg_varp_destroy(v)
