@@ -363,7 +363,9 @@ int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps);
  * tensor Gauss-Legendre rule of max(p, q) + 1 points per tangential
  * direction, where both elements' traces are evaluated and the flux is
  * formed once for both sides (conservative; where p = q it is the
- * single-degree scheme, bitwise).  One launch per degree present.
+ * single-degree scheme, bitwise).  Per RK stage one launch for the faces
+ * between degrees (each face's flux projected onto both sides), then one
+ * launch per degree present.
  * State layout: Q[f * T + off[e] + (k N_e + j) N_e + i], field f = rho, rho u,
  * rho v, rho w, rho E, T = dg_varp_num_dof, off[e] = dg_varp_offset(v, e):
  * the elements' [N_e]^3 blocks back to back, e = (ez ny + ey) nx + ex, the
@@ -396,9 +398,10 @@ int dg_varp_rk_steps(dg_varp* v, double* Q, double* res, double dt, int nsteps);
 /* Not in the paper: measurement support.  While on, every launch is
  * bracketed by HIP events (switching on clears the record). */
 int dg_varp_set_timing(dg_varp* v, int on);
-/* SYNCHRONISING.  ms[3 p + mode], count[3 p + mode] (HOST arrays of 24):
+/* SYNCHRONISING.  ms[3 p + mode], count[3 p + mode] (HOST arrays of 25):
  * summed milliseconds and launches of degree p's kernel, mode 0 right-hand
- * side, 1 RK stages 2..5, 2 the first RK stage; clears the record. */
+ * side, 1 RK stages 2..5, 2 the first RK stage; ms[24], count[24] the
+ * mortar-face kernel.  Clears the record. */
 int dg_varp_timing_read(dg_varp* v, double* ms, int64_t* count);
 
 /* Not in the paper: measurement support.  Opt-in per-launch timing for

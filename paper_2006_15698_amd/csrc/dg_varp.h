@@ -25,21 +25,37 @@ struct DGVarpTabs {
   double proj[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][DG_VARP_MAXN * DG_VARP_MAXN];
 };
 
+// A face between elements of different degrees: element a (its +d face)
+// and its +d neighbour b (their -d face); lo/hi the point counts of the
+// element of lower / higher degree; sa, sb the first double of the two
+// sides' projected fluxes ([5][N_a^2], [5][N_b^2]) in the face-flux buffer.
+struct DGVarpFace {
+  int a, b, d;
+  int code;            // (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (1 if a is the lower degree)
+  int64_t sa, sb;
+};
+
 // Mesh description read by every launch.
 struct DGVarpMesh {
-  const int* deg;          // degree per element [E]
   const int64_t* off;      // first node of every element [E] (field stride T)
+  const int64_t* slot;     // [E][6]: a face's projected flux in fbuf, -1 where conforming
   const int* list;         // elements grouped by degree, ascending inside a group
   const DGVarpTabs* tabs;
+  const DGVarpFace* faces; // the mortar faces, grouped by code
+  double* fbuf;            // projected fluxes of the mortar faces
   int64_t T;               // total nodes
   int nx, ny, nz;
-  int maxn;                // largest point count p + 1 in the mesh
+  int nfaces;
 };
 
 // Launch one stage (mode 0: RR = dQ/dt; 1: LSERK45 stage Qin -> Qout with
 // res = RR in place; 2: the first stage) over the `count` elements of degree
-// N - 1 listed from list[first].
+// N - 1 listed from list[first].  Reads the mortar fluxes that
+// dg_launch_varp_mortar wrote for the same Qin.
 int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMesh& m, int first, int count,
                    const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt);
+// The flux of every mortar face of Qin, projected onto both sides' face
+// nodes, into m.fbuf.
+int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin);
 // Elements per workgroup of the variable-degree kernel for N points.
 int dg_varp_epb(int N);

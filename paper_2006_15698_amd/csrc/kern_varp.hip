@@ -1,100 +1,251 @@
 // Variable polynomial degree per element on the periodic Cartesian mesh:
-// one fused RHS / LSERK45 stage launch per degree present.
+// per RK stage one mortar launch, then one fused RHS / LSERK45 stage launch
+// per degree present.
 //
 // The method of Section II-B on every element with its own degree (the
 // hp-adaptive setting that Sections I and III name), faces between elements
 // of degrees p and q integrated on a mortar: the Gauss-Legendre rule of
 // M = max(p, q) + 1 points per tangential direction, both traces evaluated
-// there, the local Lax-Friedrichs flux formed, and the flux integrated
-// against the element's own test functions.  With the diagonal collocated
+// there, the local Lax-Friedrichs flux formed once, and the flux integrated
+// against each side's own test functions.  With the diagonal collocated
 // mass matrix divided out, the face term of a node is the one of Eq. (5) on
 // one element, with the face flux at the element's own face nodes replaced
 // by the projection
 //     G(t1, t2) = sum_{b1, b2} P[t1][b1] P[t2][b2] F*(b1, b2),
 //     P[t][b] = l_t(x^M_b) W^M_b / w_t,
-// which is the face flux itself where M equals the element's own point count
-// (a conforming face, or a neighbour of lower degree).
+// which is F* itself on the side of higher degree (its face nodes are the
+// mortar points).
 //
-// A workgroup owns EPB elements of one degree from the degree's element
-// list, one thread per node:
+// k_varp_mortar: one wave per mortar face (faces grouped by degree pair):
+//   the lower-degree side's trace at its face nodes into LDS, the higher
+//   side's trace at its face nodes (the mortar points) in registers, the
+//   lower side's trace interpolated to the mortar points, the flux, written
+//   for the higher side and projected for the lower side into the face-flux
+//   buffer.
+// k_varp<N, MODE>: a workgroup owns EPB elements of one degree from the
+// degree's element list, one thread per node:
 //   A. the elements' states into LDS (each element's nodes are contiguous);
-//   B. face tasks (element, face) in rounds, each task on a group of GS
-//      lanes: (1) the neighbour's trace at its own face nodes, read from
-//      global memory along its normal lines, and the own trace from LDS;
-//      (2) the flux at the mortar points (interpolating a trace of fewer
-//      points); (3) the projection back to the own face nodes;
+//      one wave looks up the 6 EPB (face, element) tasks: the mortar flux's
+//      place in the buffer, or for a conforming face the neighbour's first
+//      node;
+//   B. one point per lane in 64-point slots of one face each: on a
+//      conforming face the neighbour's trace interpolated from its state
+//      along the normal line (global memory), the own trace from LDS and the
+//      flux (the chains of the single-degree kernel); on a mortar face the
+//      projected flux from the buffer;
 //   C/D. the volume contraction, lift and RK update of the single-degree
 //      neighbour-read kernel, in the same order, so that a mesh of one degree
 //      gives bitwise the results of that kernel.
 // State layout: Q[f * T + off[e] + (k N + j) N + i], T the total node count.
 
 #include "dg_varp.h"
-#include "stage_fp64.h"
+#include "stage_nb.h"
 
 namespace dgdev {
 namespace {
 
 template <int N>
 struct VCfg {
-  // elements per workgroup and threads (one per node, whole waves)
-  static constexpr int EPB = N <= 2 ? 8 : (N == 3 ? 4 : (N == 4 ? 4 : (N == 5 ? 2 : 1)));
+  // elements per workgroup and threads (one per node, whole waves); the
+  // single-degree kernel's tiles from N = 3 on (at most 64 face tasks)
+  static constexpr int EPB = N <= 2 ? 8 : (N == 3 ? 9 : (N == 4 ? 4 : (N == 5 ? 2 : 1)));
   static constexpr int NODES = EPB * N * N * N;
   static constexpr int NT = (NODES + 63) / 64 * 64;
+  static constexpr int NW = NT / 64;
   static constexpr int FP = EPB * N * N;
+  static constexpr int TASKS = 6 * EPB;          // (face, element) pairs
+  static constexpr int WPF = (FP + 63) / 64;     // 64-point slots per face
+  static constexpr int SMEM = 5 * NODES + 30 * FP + N * N + 2 * N;
+  static_assert(TASKS <= 64, "the face tasks are looked up by one wave");
 };
 
-// LDS doubles of the kernel for a face-task group size gs and a mortar
-// point stride mq2 (the largest point count squared in the mesh).
-template <int N>
-__host__ __device__ constexpr int varp_smem(int gs, int mq2) {
-  using C = VCfg<N>;
-  return 5 * C::NODES + 30 * C::FP + (C::NT / gs) * (5 * N * N + 10 * mq2) + N * N + 2 * N;
-}
-
 // Node of a degree-(n-1) element: index m along direction d, tangential
-// point (a, b) (lower tangential axis a), as tnode with a runtime n.
-__device__ __forceinline__ int rt_node(int n, int d, int m, int a, int b) {
-  if (d == 0) return m + n * (a + n * b);
-  if (d == 1) return a + n * (m + n * b);
-  return a + n * (b + n * m);
+// point (a, b) (lower tangential axis a), as tnode with a runtime d.
+template <int NN>
+__device__ __forceinline__ int rt_node(int d, int m, int a, int b) {
+  if (d == 0) return m + NN * (a + NN * b);
+  if (d == 1) return a + NN * (m + NN * b);
+  return a + NN * (b + NN * m);
 }
 
-// sum_{t2 < n} I[b2 n + t2] sum_{t1 < n} I[b1 n + t1] v[t1 + n t2]: a face
-// polynomial given at its n x n nodes, evaluated at mortar point (b1, b2).
-__device__ __forceinline__ double face_interp(const double* __restrict__ I, int n, int b1, int b2,
-                                              const double* v) {
-  double acc = 0.0;
-  for (int t2 = 0; t2 < n; ++t2) {
-    double s = 0.0;
-    for (int t1 = 0; t1 < n; ++t1) s = fma(I[b1 * n + t1], v[t1 + n * t2], s);
-    acc = fma(I[b2 * n + t2], s, acc);
+// Flux at point pt of a conforming face (D, SIDE) of an element: the own
+// trace from LDS, the neighbour's from its state at qn (global memory),
+// the chains of the single-degree kernel.
+template <int N, int D, int SIDE>
+__device__ __forceinline__ void conforming_flux(const DGTables& tb, const double* own, int ostride,
+                                                const double* __restrict__ qn, int64_t T, int pt,
+                                                const double* lmr, const double* lpr, double* fs) {
+  double nb[5], o[5];
+  chunk_trace<N, D, SIDE>(qn, T, 0, pt, lmr, lpr, nb);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double v = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v = fma(SIDE ? lpr[m] : lmr[m], own[f * ostride + tnode<N>(D, m, pt)], v);
+    o[f] = v;
   }
-  return acc;
+  lf_flux_d<D>(SIDE ? o : nb, SIDE ? nb : o, tb.gamma, tb.gm1, fs);
+}
+
+// One mortar face on one wave, lower side NLO points, higher side NHI = M
+// points per direction.  g: this wave's LDS region [5][64] (traces) +
+// [5][64] (flux).
+template <int NLO, int NHI>
+__device__ __forceinline__ void mortar_face(const DGTables& tb, const DGVarpTabs* __restrict__ tabs,
+                                            const DGVarpMesh& m, const DGVarpFace& F,
+                                            const double* __restrict__ Qin, double* g, int lane) {
+  constexpr int M = NHI, L2 = NLO * NLO, M2 = M * M;
+  const int d = F.d;
+  const bool alo = F.code & 1;          // element a (the -d side) has the lower degree
+  const int elo = alo ? F.a : F.b, ehi = alo ? F.b : F.a;
+  // a's face is its +1 face, b's its -1 face
+  const double* clo = alo ? tabs->lp[NLO] : tabs->lm[NLO];
+  const double* chi = alo ? tabs->lm[NHI] : tabs->lp[NHI];
+  const int64_t T = m.T;
+  double* gL = g;          // [5][64] lower side's trace at its face nodes
+  double* gF = g + 320;    // [5][64] flux at the mortar points
+  if (lane < L2) {
+    const double* q = Qin + m.off[elo];
+    const int a = lane % NLO, b = lane / NLO;
+    double w[5][NLO];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+#pragma unroll
+      for (int k = 0; k < NLO; ++k) w[f][k] = q[f * T + rt_node<NLO>(d, k, a, b)];
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < NLO; ++k) v = fma(clo[k], w[f][k], v);
+      gL[f * 64 + lane] = v;
+    }
+  }
+  double th[5];
+  if (lane < M2) {
+    const double* q = Qin + m.off[ehi];
+    const int a = lane % M, b = lane / M;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      double w[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) w[k] = q[f * T + rt_node<M>(d, k, a, b)];
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) v = fma(chi[k], w[k], v);
+      th[f] = v;
+    }
+  }
+  __syncwarp();
+  if (lane < M2) {
+    const double* I = tabs->interp[NLO][M];
+    const int b1 = lane % M, b2 = lane / M;
+    double r1[NLO], r2[NLO];
+#pragma unroll
+    for (int t = 0; t < NLO; ++t) {
+      r1[t] = I[b1 * NLO + t];
+      r2[t] = I[b2 * NLO + t];
+    }
+    double tl[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t2 = 0; t2 < NLO; ++t2) {
+        double s = 0.0;
+#pragma unroll
+        for (int t1 = 0; t1 < NLO; ++t1) s = fma(r1[t1], gL[f * 64 + t1 + NLO * t2], s);
+        acc = fma(r2[t2], s, acc);
+      }
+      tl[f] = acc;
+    }
+    double fs[5];
+    lf_flux(alo ? tl : th, alo ? th : tl, d, tb.gamma, tb.gm1, fs);
+    double* hhi = m.fbuf + (alo ? F.sb : F.sa);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      hhi[f * M2 + lane] = fs[f];
+      gF[f * 64 + lane] = fs[f];
+    }
+  }
+  __syncwarp();
+  if (lane < L2) {
+    const double* P = tabs->proj[NLO][M];
+    const int t1 = lane % NLO, t2 = lane / NLO;
+    double p1[M], p2[M];
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      p1[b] = P[t1 * M + b];
+      p2[b] = P[t2 * M + b];
+    }
+    double* hlo = m.fbuf + (alo ? F.sa : F.sb);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b2 = 0; b2 < M; ++b2) {
+        double s = 0.0;
+#pragma unroll
+        for (int b1 = 0; b1 < M; ++b1) s = fma(p1[b1], gF[f * 64 + b1 + M * b2], s);
+        acc = fma(p2[b2], s, acc);
+      }
+      hlo[f * L2 + lane] = acc;
+    }
+  }
+}
+
+constexpr int kMortarWaves = 4;
+
+__global__ void __launch_bounds__(64 * kMortarWaves) k_varp_mortar(const DGTables tb, const DGVarpMesh m,
+                                                                    const double* __restrict__ Qin) {
+  __shared__ double sg[kMortarWaves][640];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int fi = blockIdx.x * kMortarWaves + wave;
+  if (fi >= m.nfaces) return;   // whole waves: no workgroup barrier below
+  const DGVarpFace F = m.faces[fi];
+  const DGVarpTabs* __restrict__ tabs = m.tabs;
+  double* g = sg[wave];
+#define VARP_PAIR(LO, HI) \
+  case (LO) * (DG_VARP_MAXN + 1) + (HI): mortar_face<LO, HI>(tb, tabs, m, F, Qin, g, lane); break;
+  switch (F.code >> 1) {   // uniform over the wave
+    VARP_PAIR(1, 2) VARP_PAIR(1, 3) VARP_PAIR(1, 4) VARP_PAIR(1, 5) VARP_PAIR(1, 6) VARP_PAIR(1, 7) VARP_PAIR(1, 8)
+    VARP_PAIR(2, 3) VARP_PAIR(2, 4) VARP_PAIR(2, 5) VARP_PAIR(2, 6) VARP_PAIR(2, 7) VARP_PAIR(2, 8)
+    VARP_PAIR(3, 4) VARP_PAIR(3, 5) VARP_PAIR(3, 6) VARP_PAIR(3, 7) VARP_PAIR(3, 8)
+    VARP_PAIR(4, 5) VARP_PAIR(4, 6) VARP_PAIR(4, 7) VARP_PAIR(4, 8)
+    VARP_PAIR(5, 6) VARP_PAIR(5, 7) VARP_PAIR(5, 8)
+    VARP_PAIR(6, 7) VARP_PAIR(6, 8)
+    VARP_PAIR(7, 8)
+    default: break;
+  }
+#undef VARP_PAIR
 }
 
 template <int N, int MODE>
 __global__ void __launch_bounds__(VCfg<N>::NT) k_varp(const DGTables tb, const DGVarpMesh mesh, int first,
-                                                      int count, int gs, int mq2, const double* __restrict__ Qin,
+                                                      int count, const double* __restrict__ Qin,
                                                       double* __restrict__ Qout, double* __restrict__ RR,
                                                       double rka, double rkb, double dt) {
   using C = VCfg<N>;
-  constexpr int N2 = N * N, N3 = N2 * N, EPB = C::EPB, NODES = C::NODES, FP = C::FP, NT = C::NT;
-  extern __shared__ double smem[];
+  constexpr int N2 = N * N, N3 = N2 * N, EPB = C::EPB, NODES = C::NODES, FP = C::FP;
+  constexpr int TASKS = C::TASKS, WPF = C::WPF, NW = C::NW;
+  __shared__ double smem[C::SMEM];
+  __shared__ long long sSrc[TASKS];   // conforming: the neighbour's first node; mortar: the flux's place
+  __shared__ int sMortar[TASKS];
   double* sQ = smem;               // [5][NODES] own states; reused as sF in C
   double* sF = smem;
   double* sH = sQ + 5 * NODES;     // [6][5][FP] face flux at the own face nodes
   double* sDh = sH + 30 * FP;      // [N][N]
   double* sLiftm = sDh + N2;
   double* sLiftp = sLiftm + N;
-  double* sG = sLiftp + N;         // per group: own traces [5][N2], neighbour traces [5][mq2], mortar flux [5][mq2]
-  const int gstride = 5 * N2 + 10 * mq2;
 
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int blk0 = blockIdx.x * EPB;
   const int ne = count - blk0 < EPB ? count - blk0 : EPB;
   const int64_t T = mesh.T;
 
-  // ---- A: own states (threads past the block's nodes read element 0's first node)
+  // ---- A: own states (threads past the block's nodes read element 0's
+  //      first node), the face tasks, the 1-D tables
   const int el = tid / N3;
   const int t = tid - el * N3;
   const bool act = tid < NODES && el < ne;
@@ -103,6 +254,20 @@ __global__ void __launch_bounds__(VCfg<N>::NT) k_varp(const DGTables tb, const D
   double q[5], r[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) q[f] = Qin[f * T + gofs];
+  if (wave == 0 && lane < TASKS) {
+    // task = face * EPB + element
+    const int face = lane / EPB, fel = lane - face * EPB;
+    long long src = 0;
+    int mortar = 0;
+    if (fel < ne) {
+      const int e = mesh.list[first + blk0 + fel];
+      const long long sl = mesh.slot[(int64_t)e * 6 + face];
+      mortar = sl >= 0;
+      src = mortar ? sl : mesh.off[neighbour(mesh.nx, mesh.ny, mesh.nz, e, face >> 1, (face & 1) ? 1 : -1)];
+    }
+    sSrc[lane] = src;
+    sMortar[lane] = mortar;
+  }
   if (act) {
 #pragma unroll
     for (int f = 0; f < 5; ++f) sQ[f * NODES + tid] = q[f];
@@ -125,98 +290,41 @@ __global__ void __launch_bounds__(VCfg<N>::NT) k_varp(const DGTables tb, const D
     sLiftm[tid] = a;
     sLiftp[tid] = b;
   }
+  double lmr[N], lpr[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    lmr[m] = tb.lm[m];
+    lpr[m] = tb.lp[m];
+  }
   __syncthreads();
 
-  // ---- B: face tasks; task = face * EPB + element, so that the groups of
-  //      one wave mostly share a face direction
-  const int ng = NT / gs;
-  const int g = tid / gs, lg = tid - g * gs;
-  double* gO = sG + g * gstride;   // own traces at the own face nodes
-  double* gT = gO + 5 * N2;        // neighbour traces at its face nodes
-  double* gM = gT + 5 * mq2;       // flux at the mortar points
-  const DGVarpTabs* __restrict__ tabs = mesh.tabs;
-  const int rounds = (6 * EPB + ng - 1) / ng;
-  for (int rd = 0; rd < rounds; ++rd) {
-    const int task = rd * ng + g;
-    const int face = task / EPB, fel = task - face * EPB;
-    const bool live = task < 6 * EPB && fel < ne;
-    const int D = face >> 1, side = face & 1;
-    int nq = N, M = N;
-    if (live) {
-      const int e = mesh.list[first + blk0 + fel];
-      const int nb = neighbour(mesh.nx, mesh.ny, mesh.nz, e, D, side ? 1 : -1);
-      nq = mesh.deg[nb] + 1;
-      M = nq > N ? nq : N;
-      // (1) the neighbour's trace at its face nodes: its -1 face when ours is +1
-      const double* cq = side ? tabs->lm[nq] : tabs->lp[nq];
-      const double* qn = Qin + mesh.off[nb];
-      for (int k = lg; k < nq * nq; k += gs) {
-        const int a = k % nq, b = k / nq;
+  // ---- B: face points, 64-point slots of one face each (the face is
+  //      uniform over a wave)
+  for (int s = wave; s < 6 * WPF; s += NW) {
+    const int face = s / WPF;
+    const int i = (s - face * WPF) * 64 + lane;
+    const int fel = i / N2, pt = i - fel * N2;
+    if (i < FP && fel < ne) {
+      const int task = face * EPB + fel;
+      double fs[5];
+      if (sMortar[task]) {
+        const double* h = mesh.fbuf + sSrc[task];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) {
-          double v = 0.0;
-          for (int m = 0; m < nq; ++m) v = fma(cq[m], qn[f * T + rt_node(nq, D, m, a, b)], v);
-          gT[f * mq2 + k] = v;
+        for (int f = 0; f < 5; ++f) fs[f] = h[f * N2 + pt];
+      } else {
+        const double* qn = Qin + sSrc[task];
+        const double* own = sQ + fel * N3;
+        switch (face) {
+          case 0: conforming_flux<N, 0, 0>(tb, own, NODES, qn, T, pt, lmr, lpr, fs); break;
+          case 1: conforming_flux<N, 0, 1>(tb, own, NODES, qn, T, pt, lmr, lpr, fs); break;
+          case 2: conforming_flux<N, 1, 0>(tb, own, NODES, qn, T, pt, lmr, lpr, fs); break;
+          case 3: conforming_flux<N, 1, 1>(tb, own, NODES, qn, T, pt, lmr, lpr, fs); break;
+          case 4: conforming_flux<N, 2, 0>(tb, own, NODES, qn, T, pt, lmr, lpr, fs); break;
+          default: conforming_flux<N, 2, 1>(tb, own, NODES, qn, T, pt, lmr, lpr, fs); break;
         }
       }
-      // own trace at the own face nodes (the single-degree kernel's chain)
-      const double* own = sQ + fel * N3;
-      double co[N];
 #pragma unroll
-      for (int m = 0; m < N; ++m) co[m] = side ? tb.lp[m] : tb.lm[m];
-      for (int k = lg; k < N2; k += gs) {
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-          double v = 0.0;
-#pragma unroll
-          for (int m = 0; m < N; ++m) v = fma(co[m], own[f * NODES + rt_node(N, D, m, k % N, k / N)], v);
-          gO[f * N2 + k] = v;
-        }
-      }
-    }
-    __syncthreads();
-    // (2) flux at the M x M mortar points
-    if (live) {
-      const double* Io = tabs->interp[N][M];
-      const double* In = tabs->interp[nq][M];
-      for (int k = lg; k < M * M; k += gs) {
-        const int b1 = k % M, b2 = k / M;
-        double o[5], n[5];
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-          o[f] = M == N ? gO[f * N2 + k] : face_interp(Io, N, b1, b2, gO + f * N2);
-          n[f] = M == nq ? gT[f * mq2 + k] : face_interp(In, nq, b1, b2, gT + f * mq2);
-        }
-        double fs[5];
-        lf_flux(side ? o : n, side ? n : o, D, tb.gamma, tb.gm1, fs);
-        if (M == N) {
-#pragma unroll
-          for (int f = 0; f < 5; ++f) sH[(face * 5 + f) * FP + fel * N2 + k] = fs[f];
-        } else {
-#pragma unroll
-          for (int f = 0; f < 5; ++f) gM[f * mq2 + k] = fs[f];
-        }
-      }
-    }
-    __syncthreads();
-    // (3) projection of a finer mortar's flux onto the own face nodes
-    //     (reads only this group's region, which the next round's writes
-    //     reach only after its first barrier)
-    if (live && M > N) {
-      const double* P = tabs->proj[N][M];
-      for (int k = lg; k < N2; k += gs) {
-        const int t1 = k % N, t2 = k / N;
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-          double acc = 0.0;
-          for (int b2 = 0; b2 < M; ++b2) {
-            double s = 0.0;
-            for (int b1 = 0; b1 < M; ++b1) s = fma(P[t1 * M + b1], gM[f * mq2 + b1 + M * b2], s);
-            acc = fma(P[t2 * M + b2], s, acc);
-          }
-          sH[(face * 5 + f) * FP + fel * N2 + k] = acc;
-        }
-      }
+      for (int f = 0; f < 5; ++f) sH[(face * 5 + f) * FP + i] = fs[f];
     }
   }
   __syncthreads();   // sH complete; sQ is free for sF
@@ -287,40 +395,18 @@ __global__ void __launch_bounds__(VCfg<N>::NT) k_varp(const DGTables tb, const D
   }
 }
 
-constexpr int kMaxLds = 65536;
-
-// Smallest face-task group (most groups, fewest rounds) whose LDS fits.
-template <int N>
-int pick_gs(int mq2) {
-  constexpr int NT = VCfg<N>::NT;
-  for (int gs = 8; gs <= NT; gs *= 2) {
-    if (NT % gs) continue;
-    if (gs < N * N && gs < 64) continue;   // a conforming face in one pass
-    if (varp_smem<N>(gs, mq2) * (int)sizeof(double) <= kMaxLds) return gs;
-  }
-  return -1;
-}
-
 template <int N>
 int launch_varp_n(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, int first, int count,
                   const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt) {
   if (count <= 0) return 0;
-  const int mq2 = m.maxn * m.maxn;
-  if (mq2 < N * N || m.maxn > DG_VARP_MAXN) return (int)hipErrorInvalidValue;
-  const int gs = pick_gs<N>(mq2);
-  if (gs < 0) return (int)hipErrorInvalidConfiguration;
-  const size_t lds = (size_t)varp_smem<N>(gs, mq2) * sizeof(double);
   const unsigned grid = (unsigned)((count + VCfg<N>::EPB - 1) / VCfg<N>::EPB);
   const dim3 blk(VCfg<N>::NT);
   if (mode == 0)
-    hipLaunchKernelGGL((k_varp<N, 0>), dim3(grid), blk, lds, stream, tb, m, first, count, gs, mq2, Qin, Qout, RR,
-                       a, b, dt);
+    hipLaunchKernelGGL((k_varp<N, 0>), dim3(grid), blk, 0, stream, tb, m, first, count, Qin, Qout, RR, a, b, dt);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_varp<N, 1>), dim3(grid), blk, lds, stream, tb, m, first, count, gs, mq2, Qin, Qout, RR,
-                       a, b, dt);
+    hipLaunchKernelGGL((k_varp<N, 1>), dim3(grid), blk, 0, stream, tb, m, first, count, Qin, Qout, RR, a, b, dt);
   else
-    hipLaunchKernelGGL((k_varp<N, 2>), dim3(grid), blk, lds, stream, tb, m, first, count, gs, mq2, Qin, Qout, RR,
-                       a, b, dt);
+    hipLaunchKernelGGL((k_varp<N, 2>), dim3(grid), blk, 0, stream, tb, m, first, count, Qin, Qout, RR, a, b, dt);
   return (int)hipGetLastError();
 }
 
@@ -358,4 +444,12 @@ int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMe
     default: return (int)hipErrorInvalidValue;
   }
 #undef CALL
+}
+
+int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin) {
+  using namespace dgdev;
+  if (m.nfaces <= 0) return 0;
+  const unsigned grid = (unsigned)((m.nfaces + kMortarWaves - 1) / kMortarWaves);
+  hipLaunchKernelGGL(k_varp_mortar, dim3(grid), dim3(64 * kMortarWaves), 0, stream, tb, m, Qin);
+  return (int)hipGetLastError();
 }

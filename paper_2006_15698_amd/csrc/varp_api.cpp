@@ -27,8 +27,11 @@ double lagrange_at(const double* xi, int n, int t, double x) {
 
 struct Timed {
   hipEvent_t a, b;
-  int slot;   // 3 p + mode
+  int slot;   // 3 p + mode, or kMortarSlot
 };
+
+constexpr int kMortarSlot = 3 * DG_VARP_MAXN;
+constexpr int kSlots = kMortarSlot + 1;
 
 }  // namespace
 
@@ -41,6 +44,9 @@ struct dg_varp {
   std::vector<int> deg;          // per element
   std::vector<int64_t> off;      // E + 1
   std::vector<int> list;         // grouped by degree
+  std::vector<int64_t> slot;     // [E][6] mortar flux place, -1 where conforming
+  std::vector<DGVarpFace> faces; // mortar faces grouped by degree pair
+  int64_t fbuf_doubles = 0;
   int first[DG_VARP_MAXN + 1] = {0};   // list range of point count N
   int count[DG_VARP_MAXN + 1] = {0};
   DGTables tab[DG_VARP_MAXN + 1];
@@ -64,16 +70,18 @@ struct dg_varp {
 namespace {
 
 struct Layout {
-  size_t off_tabs, off_deg, off_off, off_list, off_q2, total;
+  size_t off_tabs, off_off, off_slot, off_list, off_faces, off_fbuf, off_q2, total;
 };
 
 Layout layout(const dg_varp* v) {
   Layout L;
   L.off_tabs = 0;
-  L.off_deg = al256(sizeof(DGVarpTabs));
-  L.off_off = L.off_deg + al256(sizeof(int) * v->E);
-  L.off_list = L.off_off + al256(sizeof(int64_t) * (v->E + 1));
-  L.off_q2 = L.off_list + al256(sizeof(int) * v->E);
+  L.off_off = al256(sizeof(DGVarpTabs));
+  L.off_slot = L.off_off + al256(sizeof(int64_t) * (v->E + 1));
+  L.off_list = L.off_slot + al256(sizeof(int64_t) * 6 * v->E);
+  L.off_faces = L.off_list + al256(sizeof(int) * v->E);
+  L.off_fbuf = L.off_faces + al256(sizeof(DGVarpFace) * v->faces.size());
+  L.off_q2 = L.off_fbuf + al256(sizeof(double) * v->fbuf_doubles);
   L.total = L.off_q2 + al256((size_t)5 * v->T * sizeof(double));
   return L;
 }
@@ -93,14 +101,16 @@ DGVarpMesh mesh_of(const dg_varp* v) {
   const Layout L = layout(v);
   DGVarpMesh m;
   m.tabs = (const DGVarpTabs*)(v->ws + L.off_tabs);
-  m.deg = (const int*)(v->ws + L.off_deg);
   m.off = (const int64_t*)(v->ws + L.off_off);
+  m.slot = (const int64_t*)(v->ws + L.off_slot);
   m.list = (const int*)(v->ws + L.off_list);
+  m.faces = (const DGVarpFace*)(v->ws + L.off_faces);
+  m.fbuf = (double*)(v->ws + L.off_fbuf);
   m.T = v->T;
   m.nx = v->nx;
   m.ny = v->ny;
   m.nz = v->nz;
-  m.maxn = v->maxn;
+  m.nfaces = (int)v->faces.size();
   return m;
 }
 
@@ -113,32 +123,42 @@ int check_pair(const dg_varp* v, const void* a, const char* an, const void* b, c
   return DG_OK;
 }
 
-// One launch per degree present, bracketed by events when timing is on.
+// Event pair around a launch when timing is on (nullptr otherwise).
+Timed* timer(dg_varp* v, int slot, int* err) {
+  *err = 0;
+  if (!v->timing || v->ev_used >= 65536) return nullptr;
+  if (v->ev.size() <= v->ev_used) {
+    Timed t;
+    *err = (int)hipEventCreate(&t.a);
+    if (*err) return nullptr;
+    *err = (int)hipEventCreate(&t.b);
+    if (*err) return nullptr;
+    v->ev.push_back(t);
+  }
+  Timed* tm = &v->ev[v->ev_used++];
+  tm->slot = slot;
+  *err = (int)hipEventRecord(tm->a, v->stream);
+  return tm;
+}
+
+// The mortar launch, then one launch per degree present.
 int launch_all(dg_varp* v, const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt) {
   const DGVarpMesh m = mesh_of(v);
+  int err = 0;
+  if (m.nfaces > 0) {
+    Timed* tm = timer(v, kMortarSlot, &err);
+    if (err) return err;
+    err = dg_launch_varp_mortar(v->stream, v->tab[1], m, Qin);
+    if (err) return err;
+    if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
+  }
   for (int N = v->maxn; N >= 1; --N) {
     if (!v->count[N]) continue;
-    Timed* tm = nullptr;
-    if (v->timing && v->ev_used < 65536) {
-      if (v->ev.size() <= v->ev_used) {
-        Timed t;
-        int err = (int)hipEventCreate(&t.a);
-        if (err) return err;
-        err = (int)hipEventCreate(&t.b);
-        if (err) return err;
-        v->ev.push_back(t);
-      }
-      tm = &v->ev[v->ev_used++];
-      tm->slot = 3 * (N - 1) + mode;
-      int err = (int)hipEventRecord(tm->a, v->stream);
-      if (err) return err;
-    }
-    int err = dg_launch_varp(v->stream, N, v->tab[N], m, v->first[N], v->count[N], Qin, Qout, RR, mode, a, b, dt);
+    Timed* tm = timer(v, 3 * (N - 1) + mode, &err);
     if (err) return err;
-    if (tm) {
-      err = (int)hipEventRecord(tm->b, v->stream);
-      if (err) return err;
-    }
+    err = dg_launch_varp(v->stream, N, v->tab[N], m, v->first[N], v->count[N], Qin, Qout, RR, mode, a, b, dt);
+    if (err) return err;
+    if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
   }
   return 0;
 }
@@ -234,6 +254,39 @@ dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double
       }
     }
   }
+  // mortar faces: every +d face whose neighbour has another degree; each
+  // side's projected flux gets its own place in the face-flux buffer
+  v->slot.assign(6 * E, -1);
+  for (int64_t e = 0; e < E; ++e) {
+    const int ex = (int)(e % nx), ey = (int)((e / nx) % ny), ez = (int)(e / ((int64_t)nx * ny));
+    for (int d = 0; d < 3; ++d) {
+      const int x = d == 0 ? (ex + 1) % nx : ex, y = d == 1 ? (ey + 1) % ny : ey, z = d == 2 ? (ez + 1) % nz : ez;
+      const int64_t nb = ((int64_t)z * ny + y) * nx + x;
+      const int na = v->deg[e] + 1, nn = v->deg[nb] + 1;
+      if (na == nn) continue;
+      DGVarpFace F;
+      F.a = (int)e;
+      F.b = (int)nb;
+      F.d = d;
+      const int lo = std::min(na, nn), hi = std::max(na, nn);
+      F.code = (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (na < nn ? 1 : 0);
+      F.sa = v->fbuf_doubles;
+      v->fbuf_doubles += 5 * (int64_t)na * na;
+      F.sb = v->fbuf_doubles;
+      v->fbuf_doubles += 5 * (int64_t)nn * nn;
+      v->slot[6 * e + 2 * d + 1] = F.sa;
+      v->slot[6 * nb + 2 * d] = F.sb;
+      v->faces.push_back(F);
+    }
+  }
+  if (v->faces.size() > 0x7fffffffu) {
+    delete v;
+    dg_set_error(DG_EUNSUPPORTED, "more than 2^31-1 faces between degrees");
+    return nullptr;
+  }
+  // waves that run together mostly take the same degree pair
+  std::stable_sort(v->faces.begin(), v->faces.end(),
+                   [](const DGVarpFace& x, const DGVarpFace& y) { return (x.code >> 1) < (y.code >> 1); });
   dg_set_error(DG_OK, "");
   return v;
 }
@@ -266,8 +319,13 @@ int dg_varp_set_workspace(dg_varp* v, void* dptr, size_t bytes) {
   v->uploaded = false;
   int err = (int)hipMemcpy(v->ws + L.off_tabs, v->htabs, sizeof(DGVarpTabs), hipMemcpyHostToDevice);
   if (err) return hipfail(err, "upload mortar tables");
-  err = (int)hipMemcpy(v->ws + L.off_deg, v->deg.data(), sizeof(int) * v->E, hipMemcpyHostToDevice);
-  if (err) return hipfail(err, "upload degrees");
+  err = (int)hipMemcpy(v->ws + L.off_slot, v->slot.data(), sizeof(int64_t) * 6 * v->E, hipMemcpyHostToDevice);
+  if (err) return hipfail(err, "upload face slots");
+  if (!v->faces.empty()) {
+    err = (int)hipMemcpy(v->ws + L.off_faces, v->faces.data(), sizeof(DGVarpFace) * v->faces.size(),
+                         hipMemcpyHostToDevice);
+    if (err) return hipfail(err, "upload mortar faces");
+  }
   err = (int)hipMemcpy(v->ws + L.off_off, v->off.data(), sizeof(int64_t) * (v->E + 1), hipMemcpyHostToDevice);
   if (err) return hipfail(err, "upload offsets");
   err = (int)hipMemcpy(v->ws + L.off_list, v->list.data(), sizeof(int) * v->E, hipMemcpyHostToDevice);
@@ -318,7 +376,7 @@ int dg_varp_set_timing(dg_varp* v, int on) {
 
 int dg_varp_timing_read(dg_varp* v, double* ms, int64_t* count) {
   if (!v || !ms || !count) return dg_set_error(DG_EINVAL, "NULL argument");
-  for (int i = 0; i < 3 * DG_VARP_MAXN; ++i) {
+  for (int i = 0; i < kSlots; ++i) {
     ms[i] = 0.0;
     count[i] = 0;
   }

@@ -537,11 +537,15 @@ def dg_varp_set_timing(v, on):
 
 def dg_varp_timing_read(v):
     """{(p, mode): (ms, launches)} for the launches recorded since timing
-    was switched on (mode 0 rhs, 1 stages 2..5, 2 first stage)."""
-    ms = (ctypes.c_double * 24)()
-    cnt = (ctypes.c_int64 * 24)()
+    was switched on (mode 0 rhs, 1 stages 2..5, 2 first stage), and
+    "mortar": (ms, launches) for the kernel of the faces between degrees."""
+    ms = (ctypes.c_double * 25)()
+    cnt = (ctypes.c_int64 * 25)()
     _check(_lib.dg_varp_timing_read(v, ms, cnt))
-    return {(i // 3, i % 3): (ms[i], cnt[i]) for i in range(24) if cnt[i]}
+    out = {(i // 3, i % 3): (ms[i], cnt[i]) for i in range(24) if cnt[i]}
+    if cnt[24]:
+        out["mortar"] = (ms[24], cnt[24])
+    return out
 
 
 class VariableDegree:
