@@ -45,6 +45,10 @@ WORKLOADS = {
                                 "the initial state: perturbed Taylor-Green vortex (seed 1, amplitude 1e-2), 16^3 "
                                 "elements, p=3, dt from CFL 0.3, Q checkpointed every 8 steps; one bench step is "
                                 "one whole gradient (forward pass, recomputation and reverse pass)"),
+    "tgv48_varp": (48, None, 50, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 48^3 elements with a degree per "
+                                 "element, 3..5 from the initial enstrophy density (p = 3 + round(|curl u|), "
+                                 "22/72/5% of the elements, 6% of the faces between two degrees), mortar faces "
+                                 "between degrees, dt from CFL 0.3 at the highest degree, 50 LSERK45 steps"),
     "batch512": (None, None, 20, "512 independent periodic meshes from seed 15698: density waves on "
                                  "[0,1]^3 and TGVs on [0,2pi]^3, n^3 elements with n uniform in 6..24, "
                                  "p uniform in 1..5, amplitudes uniform in [0.05,0.3], each mesh with "
@@ -88,6 +92,8 @@ STAGE_SOURCES = {
     "vjp": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_vjp.hip"],
     "visc": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_visc.hip"],
     "split": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_split.hip"],
+    "varp": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/dg_varp.h", "paper_2006_15698_amd/csrc/kern_varp.hip",
+                               "paper_2006_15698_amd/csrc/varp_api.cpp"],
 }
 
 
@@ -403,6 +409,139 @@ def run_batch(args):
     }
 
 
+def varp_cpu_baseline(deg, h, budget_s, m=8):
+    """The variable-degree oracle advancing RK stages on the host for about
+    ``budget_s`` seconds on an m^3-element periodic block of the same
+    element size carrying the degrees of the m^3 block of the mesh (corners
+    on a 4-element lattice) whose share of nodes per degree is closest to
+    the whole mesh's (its cost per node is then about that of the whole
+    mesh)."""
+    import numpy as np
+    import workloads as W
+    from oracle import lserk
+    from oracle.varp import VariableDegreeDG
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    def node_share(d):
+        c = np.bincount(d.ravel(), minlength=8) * (np.arange(8) + 1) ** 3
+        return c / c.sum()
+    want = node_share(deg)
+    best = None
+    for oz in range(0, deg.shape[0] - m + 1, 4):
+        for oy in range(0, deg.shape[1] - m + 1, 4):
+            for ox in range(0, deg.shape[2] - m + 1, 4):
+                blk = deg[oz:oz + m, oy:oy + m, ox:ox + m]
+                gap = float(np.abs(node_share(blk) - want).sum())
+                if best is None or gap < best[0]:
+                    best = (gap, blk)
+    dm = np.ascontiguousarray(best[1])
+    Lm = tuple(float(hd) * m for hd in h)
+    ora = VariableDegreeDG((m, m, m), dm, L=Lm)
+    Q = W.varp_state((m, m, m), dm, W.tgv_primitives, L=Lm)
+    res = np.zeros_like(Q)
+    dt = ora.dt_cfl(Q, 0.3)
+    t0 = time.perf_counter()
+    stages = 0
+    while True:
+        lserk.stage(stages % 5, Q, res, dt, ora.rhs)
+        stages += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    dof = ora.num_dof()
+    return {"value": dof * stages / el / 1e9, "unit": "GDOF-RK-stages/s", "cores": threads, "kind": "oracle",
+            "sample": f"a {m}^3-element block of the same element size with the degrees of the mesh block closest "
+                      f"to its node share per degree ({np.bincount(dm.ravel()).tolist()} elements per degree): "
+                      f"{stages} RK stages "
+                      f"({dof} nodes) in {el:.1f} s; BLAS threads {threads}, host cpu_count {os.cpu_count()}"}
+
+
+def run_varp(args):
+    """The variable-degree configuration: per stage the mortar-face launch
+    and one fused stage launch per degree."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2006_15698_amd import dg
+
+    n, _, cfg_steps, desc = WORKLOADS["tgv48_varp"]
+    K = cfg_steps if args.steps is None else args.steps
+    L = (2 * math.pi,) * 3
+    deg = W.tgv_degrees((n, n, n))
+    v = dg.VariableDegree((n, n, n), deg, L=L)
+    Qh = W.varp_state((n, n, n), deg, W.tgv_primitives, L=L)
+    # dt = CFL / ((2 p_max + 1) max over nodes of sum_d (|u_d| + c) / h_d)
+    h = np.array(L) / n
+    rho = Qh[0]
+    vel = Qh[1:4] / rho
+    c = np.sqrt(W.GAMMA * (W.GAMMA - 1) * (Qh[4] - 0.5 * rho * (vel ** 2).sum(axis=0)) / rho)
+    rate = float(np.max(sum((np.abs(vel[d]) + c) / h[d] for d in range(3))))
+    dt = 0.3 / ((2 * int(deg.max()) + 1) * rate)
+    Q0 = torch.from_numpy(Qh.reshape(-1)).cuda()
+    dof = v.num_dof()
+    Q = Q0.clone()
+    res = torch.zeros_like(Q)
+    if args.warmup > 0:
+        v.step(Q, res, dt, nsteps=args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    v.step(Q, res, dt, nsteps=K)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    value = dof * 5 * K / (ms * 1e-3) / 1e9
+    counts = np.bincount(deg.ravel(), minlength=8)
+    nodes = {int(p): int(counts[p]) * (p + 1) ** 3 for p in range(8) if counts[p]}
+    nmortar = sum(int(np.sum(deg != np.roll(deg, 1, axis=a))) for a in range(3))
+    out = {
+        "metric": "GDOF-RK-stages/sec", "value": value, "unit": "GDOF-RK-stages/sec", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": ms / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"tgv48_varp: {desc}", "elements": n ** 3, "dof": dof, "dt": dt,
+                   "elements_per_degree": {int(p): int(counts[p]) for p in range(8) if counts[p]},
+                   "mortar_faces": nmortar, "precision": "fp64"},
+    }
+    if not args.no_roofline:
+        # Per-launch HIP events on the library's stream (a second pass over
+        # the same K steps); the dominant kernel is the stage kernel of the
+        # degree with the most nodes, stages 2..5.
+        v.set_timing(1)
+        v.step(Q, res, dt, nsteps=K)
+        t = v.timing_read()
+        v.set_timing(0)
+        kernels = {}
+
+        def label(p, mode):
+            return f"k_varp p={p} {'stages 2..5' if mode == 1 else 'first stage'}"
+        for key, (k_ms, k_n) in t.items():
+            a_s = k_ms / k_n * 1e-3
+            if key == "mortar":
+                kernels["k_varp_mortar"] = {"avg_launch_us": a_s * 1e6, "launches": k_n, "faces": nmortar}
+                continue
+            p, mode = key
+            per = ALG_BYTES_PER_DOF_STAGE if mode == 1 else ALG_BYTES_PER_DOF_FIRST_STAGE
+            kernels[label(p, mode)] = {"avg_launch_us": a_s * 1e6, "launches": k_n,
+                                       "alg_bytes_per_launch": per * nodes[p], "achieved": per * nodes[p] / a_s / 1e9}
+        pdom = max(nodes, key=nodes.get)
+        dom = kernels[label(pdom, 1)]
+        out["roofline"] = {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": dom["achieved"] / HBM_PEAK_GBS,
+                           "traffic": measured_traffic("tgv48_varp", "varp", {}),
+                           "kernel": f"k_varp<{pdom + 1}> (degree {pdom}: fused RHS + LSERK45 stage, stages 2..5)",
+                           "avg_launch_us": dom["avg_launch_us"], "launches": dom["launches"],
+                           "alg_bytes_per_launch": dom["alg_bytes_per_launch"], "kernels": kernels,
+                           "stage_bytes_per_node": ALG_BYTES_PER_DOF_STAGE}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = varp_cpu_baseline(deg, h, args.cpu_seconds)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,6 +606,9 @@ def main():
         return
     if args.workload == "adjoint16_p3":
         print(json.dumps(run_adjoint(args)), flush=True)
+        return
+    if args.workload == "tgv48_varp":
+        print(json.dumps(run_varp(args)), flush=True)
         return
 
     n, p, cfg_steps, desc = WORKLOADS[args.workload]

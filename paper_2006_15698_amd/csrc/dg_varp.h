@@ -26,13 +26,13 @@ struct DGVarpTabs {
 };
 
 // A face between elements of different degrees: element a (its +d face)
-// and its +d neighbour b (their -d face); lo/hi the point counts of the
-// element of lower / higher degree; sa, sb the first double of the two
-// sides' projected fluxes ([5][N_a^2], [5][N_b^2]) in the face-flux buffer.
+// and its +d neighbour b (their -d face), with first nodes oa, ob; sa, sb
+// the first double of the two sides' projected fluxes ([5][N_a^2],
+// [5][N_b^2]) in the face-flux buffer.
 struct DGVarpFace {
-  int a, b, d;
-  int code;            // (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (1 if a is the lower degree)
-  int64_t sa, sb;
+  int64_t oa, ob, sa, sb;
+  int d;
+  int code;            // (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (1 if a has the lower degree)
 };
 
 // Mesh description read by every launch.

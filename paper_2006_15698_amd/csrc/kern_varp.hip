@@ -97,15 +97,26 @@ __device__ __forceinline__ void mortar_face(const DGTables& tb, const DGVarpTabs
   constexpr int M = NHI, L2 = NLO * NLO, M2 = M * M;
   const int d = F.d;
   const bool alo = F.code & 1;          // element a (the -d side) has the lower degree
-  const int elo = alo ? F.a : F.b, ehi = alo ? F.b : F.a;
   // a's face is its +1 face, b's its -1 face
   const double* clo = alo ? tabs->lp[NLO] : tabs->lm[NLO];
   const double* chi = alo ? tabs->lm[NHI] : tabs->lp[NHI];
   const int64_t T = m.T;
   double* gL = g;          // [5][64] lower side's trace at its face nodes
   double* gF = g + 320;    // [5][64] flux at the mortar points
+  // the interpolation rows of mortar point (b1, b2), loaded while the state
+  // lines are in flight
+  double r1[NLO], r2[NLO];
+  {
+    const double* I = tabs->interp[NLO][M];
+    const int b1 = lane % M, b2 = (lane < M2 ? lane : 0) / M;
+#pragma unroll
+    for (int t = 0; t < NLO; ++t) {
+      r1[t] = I[b1 * NLO + t];
+      r2[t] = I[b2 * NLO + t];
+    }
+  }
   if (lane < L2) {
-    const double* q = Qin + m.off[elo];
+    const double* q = Qin + (alo ? F.oa : F.ob);
     const int a = lane % NLO, b = lane / NLO;
     double w[5][NLO];
 #pragma unroll
@@ -123,7 +134,7 @@ __device__ __forceinline__ void mortar_face(const DGTables& tb, const DGVarpTabs
   }
   double th[5];
   if (lane < M2) {
-    const double* q = Qin + m.off[ehi];
+    const double* q = Qin + (alo ? F.ob : F.oa);
     const int a = lane % M, b = lane / M;
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
@@ -138,14 +149,6 @@ __device__ __forceinline__ void mortar_face(const DGTables& tb, const DGVarpTabs
   }
   __syncwarp();
   if (lane < M2) {
-    const double* I = tabs->interp[NLO][M];
-    const int b1 = lane % M, b2 = lane / M;
-    double r1[NLO], r2[NLO];
-#pragma unroll
-    for (int t = 0; t < NLO; ++t) {
-      r1[t] = I[b1 * NLO + t];
-      r2[t] = I[b2 * NLO + t];
-    }
     double tl[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
@@ -221,7 +224,7 @@ __global__ void __launch_bounds__(64 * kMortarWaves) k_varp_mortar(const DGTable
 }
 
 template <int N, int MODE>
-__global__ void __launch_bounds__(VCfg<N>::NT) k_varp(const DGTables tb, const DGVarpMesh mesh, int first,
+__global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(N == 4 ? 4 : 1, 8))) k_varp(const DGTables tb, const DGVarpMesh mesh, int first,
                                                       int count, const double* __restrict__ Qin,
                                                       double* __restrict__ Qout, double* __restrict__ RR,
                                                       double rka, double rkb, double dt) {

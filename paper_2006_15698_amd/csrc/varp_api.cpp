@@ -265,8 +265,8 @@ dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double
       const int na = v->deg[e] + 1, nn = v->deg[nb] + 1;
       if (na == nn) continue;
       DGVarpFace F;
-      F.a = (int)e;
-      F.b = (int)nb;
+      F.oa = v->off[e];
+      F.ob = v->off[nb];
       F.d = d;
       const int lo = std::min(na, nn), hi = std::max(na, nn);
       F.code = (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (na < nn ? 1 : 0);
