@@ -52,7 +52,8 @@ WORKLOADS = {
     "batch512": (None, None, 20, "512 independent periodic meshes from seed 15698: density waves on "
                                  "[0,1]^3 and TGVs on [0,2pi]^3, n^3 elements with n uniform in 6..24, "
                                  "p uniform in 1..5, amplitudes uniform in [0.05,0.3], each mesh with "
-                                 "its own CFL-0.3 dt; one graph-replayed launch per RK stage"),
+                                 "its own CFL-0.3 dt; per RK stage one launch per degree present, "
+                                 "graph-replayed"),
 }
 
 
@@ -78,7 +79,7 @@ def flops_per_dof_stage(N):
 # The device sources each measured kernel is built from (the C ABI header
 # only declares host entry points), per kernel family: the
 # single-mesh stage kernel in either precision (neighbour-read form, its
-# tables and launch parameters), the batched persistent kernel and the
+# tables and launch parameters), the batched kernels and the
 # neighbour-read adjoint kernel.
 _COMMON_SOURCES = ["paper_2006_15698_amd/csrc/dg_internal.h",
                    "paper_2006_15698_amd/csrc/stage_fp64.h", "paper_2006_15698_amd/csrc/stage_nb.h"]
@@ -398,13 +399,18 @@ def run_batch(args):
         "dtype": "f64" if args.precision == "fp64" else "f32 contractions, f64 state",
         "data": "synthetic",
         "config": {"workload": f"batch512: {desc}", "meshes": len(specs), "dof": dof,
-                   "meshes_per_degree": degs, "tiles": b.tiles, "precision": args.precision},
+                   "meshes_per_degree": degs, "tiles": b.tiles, "precision": args.precision,
+                   "options": b.options()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("batch512", "batch", {"precision": args.precision,
                                                                        "tiles": {str(k): v for k, v in
-                                                                                 sorted(b.tiles.items())}}),
-                     "kernel": "k_batch_stage (persistent, all meshes)", "avg_launch_us": avg_s * 1e6,
+                                                                                 sorted(b.tiles.items())},
+                                                                       "options": b.options()}),
+                     "kernel": ("k_batch_degree<N, EPB> (one launch per degree present; the five launches of "
+                                "one RK stage timed together)"
+                                if b.options()["batch_launch"] == dg.DG_BATCH_PER_DEGREE
+                                else "k_batch_stage (persistent, all meshes)"), "avg_launch_us": avg_s * 1e6,
                      "alg_bytes_per_launch": ALG_BYTES_PER_DOF_STAGE * dof},
     }
 

@@ -160,10 +160,12 @@ enum {
   DG_OPT_XCD_REMAP = 2,
   DG_OPT_ORDER = 3,
   DG_OPT_PENCIL_X = 4,
-  DG_OPT_PENCIL_Z = 5
+  DG_OPT_PENCIL_Z = 5,
+  DG_OPT_BATCH_LAUNCH = 6   /* batched meshes only (dg_batch_set_option) */
 };
 enum { DG_EXCHANGE_TRACES = 0, DG_EXCHANGE_NEIGHBOUR = 1 };
 enum { DG_ORDER_LINEAR = 0, DG_ORDER_PENCIL = 1 };
+enum { DG_BATCH_PERSISTENT = 0, DG_BATCH_PER_DEGREE = 1 };
 /* DG_EINVAL for an unknown key or a value out of range. */
 int dg_set_option(dg_ctx* ctx, int key, int value);
 /* Current value of an option into *value. */
@@ -295,9 +297,10 @@ int dg_recip_sqrt(const double* x, double* r, double* s, int64_t n, void* hip_st
  * Not in the paper: an extension of its hot path to many small problems on
  * one GPU (the per-mesh arithmetic is that of Section II-B and Sections
  * IV-V, unchanged).  Many independent periodic meshes of uneven size and degree advanced
- * together: one persistent launch per RK stage walks a work list of
- * (mesh, element block) items, with a per-degree code path and per-degree
- * elements-per-workgroup tile (dg_batch_set_tile).  The arithmetic on every
+ * together: per RK stage one launch per degree present (or one persistent
+ * launch, DG_OPT_BATCH_LAUNCH) over a work list of (mesh, element block)
+ * items, with a per-degree code path and per-degree elements-per-workgroup
+ * tile (dg_batch_set_tile).  The arithmetic on every
  * element is the one of the single-mesh entry points above, so each mesh's
  * result is bitwise that of a single-mesh context on the same state.
  * State layout: one device array holding the meshes back to back; mesh i
@@ -316,18 +319,27 @@ int dg_batch_set_precision(dg_batch* b, int mode);
  * dg_batch_tile_options); changes the work list, so call it before
  * dg_batch_set_workspace. */
 int dg_batch_set_tile(dg_batch* b, int p, int epb);
-/* Order in which the persistent launch walks the work list; the results are
- * bitwise the same for every setting.  Keys as for dg_set_option:
- * DG_OPT_XCD_REMAP 1 cuts every degree group of the work list into 8
- *   contiguous parts of equal node count and gives part x of each group to
- *   XCD x of the MI355X, so that every XCD runs the same mix of degrees and
- *   the items that run at the same time on one XCD are neighbours in the
- *   list and share its L2; 0 (default) deals every item to the whole grid
- *   round robin.
- * DG_OPT_ORDER: items of a mesh row by row (DG_ORDER_LINEAR, default) or in
+/* Launch form and the order in which the launches walk the work list; the
+ * results are bitwise the same for every setting.  Keys as for
+ * dg_set_option:
+ * DG_OPT_XCD_REMAP 1: with one launch per degree, each XCD of the MI355X
+ *   takes a contiguous part of the degree's items; with the persistent
+ *   launch, every degree group of the work list is cut into 8 contiguous
+ *   parts of equal node count and XCD x gets part x of each group, so that
+ *   every XCD runs the same mix of degrees.  Either way the items that run
+ *   at the same time on one XCD are neighbours in the list and share its
+ *   L2; 0 (default) leaves the round-robin spread of workgroups.
+ * DG_OPT_ORDER: items of a mesh row by row (DG_ORDER_LINEAR) or in
  *   pencils of DG_OPT_PENCIL_X elements (0 = the whole row) by
- *   DG_OPT_PENCIL_Z planes swept along y (DG_ORDER_PENCIL; 16 x 8 when
- *   chosen), which lists an item's y- and z-neighbours close to it.
+ *   DG_OPT_PENCIL_Z planes swept along y (DG_ORDER_PENCIL, default, 16 x 8),
+ *   which lists an item's y- and z-neighbours close to it.
+ * DG_OPT_BATCH_LAUNCH: DG_BATCH_PER_DEGREE (default) runs a stage as one
+ *   launch per degree present over that degree's items (one workgroup per
+ *   item, each (degree, tile) variant its own kernel and register
+ *   allocation; with DG_OPT_XCD_REMAP each XCD takes a contiguous part of
+ *   the degree's items); DG_BATCH_PERSISTENT as one persistent launch over
+ *   the whole work list with every variant in one kernel (the register
+ *   allocation of the largest variant for all).
  * The work list is rebuilt (and re-uploaded, SYNCHRONISING, when a
  * workspace is set); DG_EINVAL for an unknown key or a value out of range. */
 int dg_batch_set_option(dg_batch* b, int key, int value);
@@ -345,12 +357,13 @@ int dg_batch_set_workspace(dg_batch* b, void* dptr, size_t bytes);
 int dg_batch_set_dt(dg_batch* b, const double* dt);
 /* R = dQ/dt of every mesh. */
 int dg_batch_rhs(dg_batch* b, const double* Q, double* R);
-/* nsteps LSERK45 steps of every mesh with its own dt: one persistent
- * launch per stage; the state alternates between Q and a workspace buffer
- * (an odd nsteps ends with one device-to-device copy back into Q). */
+/* nsteps LSERK45 steps of every mesh with its own dt (per stage the
+ * launches of DG_OPT_BATCH_LAUNCH); the state alternates between Q and a
+ * workspace buffer (an odd nsteps ends with one device-to-device copy back
+ * into Q). */
 int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps);
-/* Same result as dg_batch_rk_steps, with the five stage launches of a step
- * replayed from HIP graphs (captured on first use for this (Q, res) pair and
+/* Same result as dg_batch_rk_steps, with the launches of a step's five
+ * stages replayed from HIP graphs (captured on first use for this (Q, res) pair and
  * step parity; recaptured when the pointers change). */
 int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps);
 

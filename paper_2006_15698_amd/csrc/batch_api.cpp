@@ -36,15 +36,18 @@ struct dg_batch {
   const double* gR = nullptr;
   int gprec = -1;
   unsigned grid[2] = {0, 0};   // persistent grid per precision (FP64, FP32 form)
-  // visiting order of the work list (dg_batch_set_option)
-  // defaults: the measured rates on the 512-mesh workload are within 1.5%
-  // of each other for every setting (the XCD split +1.5% in FP64, -1% in
-  // the FP32 form; pencils within 1%)
+  // launch form and visiting order of the work list (dg_batch_set_option).
+  // Defaults: the fastest measured on the 512-mesh workload: one launch per
+  // degree (20.1 against 14.5 GDOF-stages/s for the persistent launch in
+  // FP64, 16.9 against 11.4 in the FP32 form), pencil order; the XCD remap
+  // and the order move the per-degree rates by under 2%
   int xcd = 0;                 // each XCD walks its own contiguous part of the list
-  int order = DG_ORDER_LINEAR; // item order within a mesh
+  int order = DG_ORDER_PENCIL; // item order within a mesh
   int pencil_x = 16;           // elements of a pencil along x (0 = whole row)
   int pencil_z = 8;            // element planes of a pencil along z
+  int launch = DG_BATCH_PER_DEGREE;
   DGBatchSplit split{};
+  int vbegin[DG_MAXN + 1] = {0}, vcount[DG_MAXN + 1] = {0};   // items per point count
 };
 
 namespace {
@@ -101,8 +104,14 @@ void build_items(dg_batch* b) {
   // contiguous parts of equal node count, and XCD x gets part x of every
   // group, so each XCD runs the same mix of degrees (equal node counts of one
   // degree are equal work) on neighbouring items
-  b->split.xcd = b->xcd;
-  if (b->xcd) {
+  for (int N = 0; N <= DG_MAXN; ++N) b->vbegin[N] = b->vcount[N] = 0;
+  for (size_t k = 0; k < b->items.size(); ++k) {
+    const int N = b->inst[b->items[k].x].N;
+    if (!b->vcount[N]) b->vbegin[N] = (int)k;
+    ++b->vcount[N];
+  }
+  b->split.xcd = b->xcd && b->launch == DG_BATCH_PERSISTENT;
+  if (b->split.xcd) {
     std::vector<int2> out;
     out.reserve(b->items.size());
     std::vector<size_t> group = {0};
@@ -148,6 +157,13 @@ DGBatchLaunch launch_of(const dg_batch* b, hipStream_t s) {
   l.grid = b->grid[l.f32];
   l.stream = s;
   l.split = b->split;
+  l.per_degree = b->launch == DG_BATCH_PER_DEGREE;
+  l.xcd = b->xcd;
+  for (int N = 0; N <= DG_MAXN; ++N) {
+    l.vbegin[N] = b->vbegin[N];
+    l.vcount[N] = b->vcount[N];
+    l.epb[N] = b->epb_for_N[N];
+  }
   // the XCD split needs the same number of workgroups on every XCD
   if (l.split.xcd) l.grid = l.grid >= 8 ? l.grid / 8 * 8 : 8;
   return l;
@@ -308,6 +324,11 @@ int dg_batch_set_option(dg_batch* b, int key, int value) {
       if (value < 1) return dg_set_error(DG_EINVAL, "pencil z extent %d < 1", value);
       b->pencil_z = value;
       break;
+    case DG_OPT_BATCH_LAUNCH:
+      if (value != DG_BATCH_PERSISTENT && value != DG_BATCH_PER_DEGREE)
+        return dg_set_error(DG_EINVAL, "unknown batch launch form %d", value);
+      b->launch = value;
+      break;
     default: return dg_set_error(DG_EINVAL, "unknown batch option %d", key);
   }
   // the work list is rebuilt in place (same length): re-upload it
@@ -328,6 +349,7 @@ int dg_batch_get_option(const dg_batch* b, int key, int* value) {
   if (!b || !value) return dg_set_error(DG_EINVAL, "NULL argument");
   switch (key) {
     case DG_OPT_XCD_REMAP: *value = b->xcd; return DG_OK;
+    case DG_OPT_BATCH_LAUNCH: *value = b->launch; return DG_OK;
     case DG_OPT_ORDER: *value = b->order; return DG_OK;
     case DG_OPT_PENCIL_X: *value = b->pencil_x; return DG_OK;
     case DG_OPT_PENCIL_Z: *value = b->pencil_z; return DG_OK;

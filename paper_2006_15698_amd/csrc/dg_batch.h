@@ -32,6 +32,12 @@ struct DGBatchLaunch {
   hipStream_t stream;
   int f32;
   DGBatchSplit split;
+  // one launch per degree (DG_BATCH_PER_DEGREE): the items of point count N
+  // are items[vbegin[N] .. vbegin[N] + vcount[N]), all with tile epb[N];
+  // xcd: each XCD takes a contiguous part of them
+  int per_degree;
+  int xcd;
+  int vbegin[DG_MAXN + 1], vcount[DG_MAXN + 1], epb[DG_MAXN + 1];
 };
 
 int dg_batch_tile_list(int N, int* out, int max);

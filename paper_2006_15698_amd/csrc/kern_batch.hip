@@ -1,15 +1,21 @@
-// Batched persistent kernels: many independent periodic meshes of uneven
-// size and polynomial degree advanced by one launch per RK stage.
+// Batched kernels: many independent periodic meshes of uneven size and
+// polynomial degree advanced together, per RK stage either one launch per
+// degree present (k_batch_degree, the default) or one persistent launch
+// (k_batch_stage).
 //
 // A work list of (mesh, first element) items, one item per block of up to
-// EPB consecutive elements of one x-row, is walked by a persistent grid
-// (static round robin: item k belongs to block k mod gridDim).  Each item
-// runs the same fused
-// neighbour-read stage body as the single-mesh kernel (stage_nb.h /
-// stage_nb32.h) with the compile-time degree N and elements-per-workgroup
-// EPB of its mesh, on a shared-memory buffer sized for the largest (N, EPB)
-// variant.  Every variant uses 256 threads.  The state of all meshes
-// alternates between two buffers (Qin -> Qout) from launch to launch.
+// EPB consecutive elements of one x-row, grouped by degree.  Each item runs
+// the same fused neighbour-read stage body as the single-mesh kernel
+// (stage_nb.h / stage_nb32.h) with the compile-time degree N and
+// elements-per-workgroup EPB of its mesh; every variant uses 256 threads.
+//   k_batch_degree<N, EPB>: one workgroup per item of one degree, with that
+//     variant's own registers and shared memory.
+//   k_batch_stage: a persistent grid walks the whole list (static round
+//     robin: item k belongs to block k mod gridDim) through a shared-memory
+//     buffer sized for the largest variant; its register allocation is the
+//     union of all variants.
+// The state of all meshes alternates between two buffers (Qin -> Qout) from
+// launch to launch; the launches of one stage read only Qin.
 
 #include "dg_batch.h"
 #include "stage_fp32.h"
@@ -96,6 +102,52 @@ k_batch_stage(const DGBatchInst* __restrict__ inst, const int2* __restrict__ ite
   }
 }
 
+// One (N, EPB) variant over its own items, one workgroup per item
+// (DG_BATCH_PER_DEGREE): the variant's own register allocation and shared
+// memory.  With xcd set, workgroup w takes item xcd_block(w): each XCD a
+// contiguous part of the items.
+template <int N, int EPB, int MODE, bool F32>
+__global__ void __launch_bounds__(BNT)
+k_batch_degree(const DGBatchInst* __restrict__ inst, const int2* __restrict__ items, int begin, int xcd,
+               const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR, double a,
+               double b, int first) {
+  __shared__ double smem[F32 ? (smax32<N, EPB>() + 7) / 8 : smax64<N, EPB>()];
+  const int w = xcd ? dgdev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int2 it = items[begin + w];
+  const int mi = __builtin_amdgcn_readfirstlane(it.x);
+  const int e0 = __builtin_amdgcn_readfirstlane(it.y);
+  const DGBatchInst& I = inst[mi];
+  const double* qi = Qin + I.qoff;
+  double* qo = Qout ? Qout + I.qoff : nullptr;
+  double* rr = RR + I.qoff;
+  const int x0 = e0 % I.tab.nx;
+  const int ne = dgdev::imin(EPB, I.tab.nx - x0);
+  if (F32)
+    dgdev::stage_nb32_body<N, MODE, EPB, BNT, dgdev::LINES_POINT>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem,
+                                                                  threadIdx.x);
+  else
+    dgdev::stage_nb_body<N, MODE, EPB, BNT, kLines64<N>>(I.tab, qi, qo, rr, a, b, I.dt, first, e0, ne, smem,
+                                                         threadIdx.x);
+}
+
+template <int N, int EPB>
+void launch_degree(const DGBatchLaunch& L, int mode, const double* Qin, double* Qout, double* RR, double a, double b,
+                   int first) {
+  const dim3 grid((unsigned)L.vcount[N]), blk(BNT);
+  const int begin = L.vbegin[N];
+#define DG_LD(m, f)                                                                                               \
+  hipLaunchKernelGGL((k_batch_degree<N, EPB, m, f>), grid, blk, 0, L.stream, L.inst, L.items, begin, L.xcd, Qin, \
+                     Qout, RR, a, b, first)
+  if (L.f32) {
+    if (mode == 0) DG_LD(0, true);
+    else DG_LD(1, true);
+  } else {
+    if (mode == 0) DG_LD(0, false);
+    else DG_LD(1, false);
+  }
+#undef DG_LD
+}
+
 }  // namespace
 
 int dg_batch_tile_list(int N, int* out, int max) {
@@ -109,6 +161,23 @@ int dg_batch_tile_list(int N, int* out, int max) {
 
 int dg_batch_launch_stage(const DGBatchLaunch& L, int mode, const double* Qin, double* Qout, double* RR, double a,
                           double b, int first) {
+  if (L.per_degree) {
+    // highest degree first (the costliest launch starts first)
+    for (int N = DG_MAXN; N >= 1; --N) {
+      if (!L.vcount[N]) continue;
+      const int key = N * 64 + L.epb[N];
+#define DG_CASE(n, e) \
+  case n * 64 + e: launch_degree<n, e>(L, mode, Qin, Qout, RR, a, b, first); break;
+      switch (key) {
+        DG_BATCH_VARIANTS(DG_CASE)
+        default: return (int)hipErrorInvalidValue;
+      }
+#undef DG_CASE
+      const int err = (int)hipGetLastError();
+      if (err) return err;
+    }
+    return 0;
+  }
 #define DG_L(m, f)                                                                                           \
   hipLaunchKernelGGL((k_batch_stage<m, f>), dim3(L.grid), dim3(BNT), 0, L.stream, L.inst, L.items, L.nitems, \
                      L.split, Qin, Qout, RR, a, b, first)

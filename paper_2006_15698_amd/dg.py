@@ -47,8 +47,13 @@ DG_EXCHANGE_TRACES = 0
 DG_EXCHANGE_NEIGHBOUR = 1
 DG_ORDER_LINEAR = 0
 DG_ORDER_PENCIL = 1
+DG_OPT_BATCH_LAUNCH = 6
+DG_BATCH_PERSISTENT = 0
+DG_BATCH_PER_DEGREE = 1
 OPTION_NAMES = {DG_OPT_EXCHANGE: "exchange", DG_OPT_XCD_REMAP: "xcd_remap", DG_OPT_ORDER: "order",
                 DG_OPT_PENCIL_X: "pencil_x", DG_OPT_PENCIL_Z: "pencil_z"}
+BATCH_OPTION_NAMES = {DG_OPT_XCD_REMAP: "xcd_remap", DG_OPT_ORDER: "order", DG_OPT_PENCIL_X: "pencil_x",
+                      DG_OPT_PENCIL_Z: "pencil_z", DG_OPT_BATCH_LAUNCH: "batch_launch"}
 
 ERROR_NAMES = {DG_EINVAL: "DG_EINVAL", DG_EUNSUPPORTED: "DG_EUNSUPPORTED", DG_EHIP: "DG_EHIP",
                DG_EALIAS: "DG_EALIAS", DG_ENONPHYSICAL: "DG_ENONPHYSICAL",
@@ -457,13 +462,13 @@ class Batch:
 
     def set_option(self, key, value):
         """Work-list visiting order (DG_OPT_XCD_REMAP, DG_OPT_ORDER,
-        DG_OPT_PENCIL_X, DG_OPT_PENCIL_Z); results are bitwise unchanged."""
+        DG_OPT_PENCIL_X, DG_OPT_PENCIL_Z) and launch form
+        (DG_OPT_BATCH_LAUNCH); results are bitwise unchanged."""
         self._s()
         dg_batch_set_option(self.b, key, value)
 
     def options(self):
-        return {name: dg_batch_get_option(self.b, k) for k, name in OPTION_NAMES.items()
-                if k != DG_OPT_EXCHANGE}
+        return {name: dg_batch_get_option(self.b, k) for k, name in BATCH_OPTION_NAMES.items()}
 
     def set_dt(self, dt):
         self._s()

@@ -71,7 +71,8 @@ def tune(meshes=16, n=16, steps=4, path=TUNED_PATH, verbose=True):
             rec = json.load(f)
     rec[dev] = {"tiles": {str(k): v for k, v in tiles.items()},
                 "ms_per_step": {str(k): {str(e): v for e, v in t.items()} for k, t in times.items()},
-                "workload": f"{meshes} meshes of {n}^3 elements per degree, {steps} graph steps"}
+                "workload": f"{meshes} meshes of {n}^3 elements per degree, {steps} graph steps, "
+                            f"the default launch form (one launch per degree)"}
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     return tiles

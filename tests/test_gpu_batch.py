@@ -137,15 +137,19 @@ def test_batch_errors(dgm):
 
 def test_batch_visiting_orders_bitwise_equal(dgm):
     """Every work-list order (row or pencil order inside a mesh, XCD split
-    on or off, ragged pencils) gives bitwise the same steps."""
+    on or off, ragged pencils) and both launch forms (one persistent launch,
+    one launch per degree) give bitwise the same steps."""
     import torch
     specs = _specs(12, 19, 2, 7)
     b, states, Q0 = _setup(dgm, specs)
     b.set_dt(_dts(specs, states))
     ref = None
-    for xcd, order, px, pz in [(0, dgm.DG_ORDER_LINEAR, 0, 1), (1, dgm.DG_ORDER_LINEAR, 0, 1),
-                               (0, dgm.DG_ORDER_PENCIL, 3, 2), (1, dgm.DG_ORDER_PENCIL, 16, 8),
-                               (1, dgm.DG_ORDER_PENCIL, 5, 3)]:
+    P, D = dgm.DG_BATCH_PERSISTENT, dgm.DG_BATCH_PER_DEGREE
+    for launch, xcd, order, px, pz in [(P, 0, dgm.DG_ORDER_LINEAR, 0, 1), (P, 1, dgm.DG_ORDER_LINEAR, 0, 1),
+                                       (P, 0, dgm.DG_ORDER_PENCIL, 3, 2), (P, 1, dgm.DG_ORDER_PENCIL, 16, 8),
+                                       (P, 1, dgm.DG_ORDER_PENCIL, 5, 3), (D, 0, dgm.DG_ORDER_LINEAR, 0, 1),
+                                       (D, 1, dgm.DG_ORDER_LINEAR, 0, 1), (D, 1, dgm.DG_ORDER_PENCIL, 5, 3)]:
+        b.set_option(dgm.DG_OPT_BATCH_LAUNCH, launch)
         b.set_option(dgm.DG_OPT_XCD_REMAP, xcd)
         b.set_option(dgm.DG_OPT_ORDER, order)
         b.set_option(dgm.DG_OPT_PENCIL_X, px)
@@ -156,4 +160,4 @@ def test_batch_visiting_orders_bitwise_equal(dgm):
         torch.cuda.synchronize()
         if ref is None:
             ref = Q
-        assert torch.equal(Q, ref), (xcd, order, px, pz)
+        assert torch.equal(Q, ref), (launch, xcd, order, px, pz)

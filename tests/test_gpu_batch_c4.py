@@ -1,10 +1,12 @@
 """The batched workload at its real size: 512 independent meshes from seed
 15698 (n^3 elements with n in 6..24, p in 1..5; 205 M nodes, 934,075 work
-items), advanced by one persistent launch per RK stage whose grid holds only
-the resident workgroups, so that every workgroup walks about 1,200 items of
-mixed (degree, tile) variants through one shared-memory buffer.
+items), advanced by one launch per degree and RK stage (the default), and
+by the persistent launch whose grid holds only the resident workgroups, so
+that every workgroup walks about 1,200 items of mixed (degree, tile)
+variants through one shared-memory buffer.
 
-Checked here, in both the FP64 and the FP32 matrix-core form:
+Checked here, in both the FP64 and the FP32 matrix-core form, on the
+default launch form:
   - 20 sampled meshes (four per degree: the largest n, the smallest n and two
     seeded picks) bitwise against single-mesh contexts on the same state and
     dt: one right-hand side and two graph-replayed steps (state and residual);
@@ -12,7 +14,9 @@ Checked here, in both the FP64 and the FP32 matrix-core form:
     steps, whole mesh (FP64: 1e-12 of the state per field; the FP32 form's
     L2 error is printed per degree and held to a stated bound);
   - the two largest p = 5 meshes (24^3) against the oracle on sampled
-    elements of the batched right-hand side (3x3x3 periodic patches).
+    elements of the batched right-hand side (3x3x3 periodic patches);
+and the persistent launch bitwise equal to it over the whole batch
+(right-hand side, state and residual).
 """
 
 import numpy as np
@@ -111,7 +115,7 @@ def _oracle_small(c4, Q, p):
 
 
 @pytest.mark.timeout(400)
-def test_c4_fp64_persistent_batch(dgm, c4):
+def test_c4_fp64_batch(dgm, c4):
     R, Q, res = _run(dgm, c4, dgm.DG_FP64)
     _bitwise_vs_single(dgm, c4, dgm.DG_FP64, R, Q, res)
     for p in range(1, 6):
@@ -156,7 +160,7 @@ FP32_STATE_BOUND = 1e-8
 
 
 @pytest.mark.timeout(400)
-def test_c4_fp32_persistent_batch(dgm, c4):
+def test_c4_fp32_batch(dgm, c4):
     R, Q, res = _run(dgm, c4, dgm.DG_FP32_MFMA)
     try:
         _bitwise_vs_single(dgm, c4, dgm.DG_FP32_MFMA, R, Q, res)
@@ -169,3 +173,31 @@ def test_c4_fp32_persistent_batch(dgm, c4):
             assert e_state <= FP32_STATE_BOUND, (p, e_state)
     finally:
         dgm.dg_batch_set_precision(c4["b"].b, dgm.DG_FP64)
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c4_persistent_launch_equals_per_degree(dgm, c4, prec):
+    """The same batch run as one persistent launch per stage
+    (DG_BATCH_PERSISTENT, XCD split on and off) gives bitwise the default
+    per-degree launches' right-hand side, state and residual over the whole
+    batch, as does the per-degree form with the XCD remap."""
+    import torch
+    mode = dgm.DG_FP64 if prec == "fp64" else dgm.DG_FP32_MFMA
+    b = c4["b"]
+    assert b.options()["batch_launch"] == dgm.DG_BATCH_PER_DEGREE
+    try:
+        R0, Q0, r0 = _run(dgm, c4, mode)
+        for launch, xcd in ((dgm.DG_BATCH_PERSISTENT, 0), (dgm.DG_BATCH_PERSISTENT, 1),
+                            (dgm.DG_BATCH_PER_DEGREE, 1)):
+            b.set_option(dgm.DG_OPT_BATCH_LAUNCH, launch)
+            b.set_option(dgm.DG_OPT_XCD_REMAP, xcd)
+            R, Q, res = _run(dgm, c4, mode)
+            same = (torch.equal(R, R0), torch.equal(Q, Q0), torch.equal(res, r0))
+            print(f"[c4 {prec}] launch form {launch}, xcd {xcd}: bitwise {same}", flush=True)
+            assert all(same)
+            del R, Q, res
+    finally:
+        b.set_option(dgm.DG_OPT_BATCH_LAUNCH, dgm.DG_BATCH_PER_DEGREE)
+        b.set_option(dgm.DG_OPT_XCD_REMAP, 0)
+        dgm.dg_batch_set_precision(b.b, dgm.DG_FP64)
