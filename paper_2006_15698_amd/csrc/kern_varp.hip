@@ -23,7 +23,8 @@
 //   for the higher side and projected for the lower side into the face-flux
 //   buffer.
 // k_varp<N, MODE>: a workgroup owns EPB elements of one degree from the
-// degree's element list, one thread per node:
+// degree's element list (in pencil order; each XCD takes a contiguous part),
+// one thread per node:
 //   A. the elements' states into LDS (each element's nodes are contiguous);
 //      one wave looks up the 6 EPB (face, element) tasks: the mortar flux's
 //      place in the buffer, or for a conforming face the neighbour's first
@@ -243,7 +244,9 @@ __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_e
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int blk0 = blockIdx.x * EPB;
+  // each XCD takes a contiguous part of the list (workgroups are dealt to
+  // the 8 XCDs round robin)
+  const int blk0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
   const int ne = count - blk0 < EPB ? count - blk0 : EPB;
   const int64_t T = mesh.T;
 

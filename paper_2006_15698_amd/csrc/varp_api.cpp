@@ -31,6 +31,10 @@ struct Timed {
 };
 
 constexpr int kMortarSlot = 3 * DG_VARP_MAXN;
+// pencil of the element lists' visiting order (elements along x, planes
+// along z), as the single-degree kernel's default
+constexpr int kPencilX = 16;
+constexpr int kPencilZ = 8;
 constexpr int kSlots = kMortarSlot + 1;
 
 }  // namespace
@@ -220,7 +224,11 @@ dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double
   }
   v->off[E] = T;
   v->T = T;
-  // element lists by degree (ascending element index inside a degree)
+  // element lists by degree, each in the single-degree kernel's visiting
+  // order: z-slabs of kPencilZ planes, inside a slab pencils of kPencilX
+  // elements along x, inside a pencil y-row by y-row, then z, x fastest (an
+  // element's y- and z-neighbours of the same degree are listed close to
+  // it, so their reads meet in L2)
   std::vector<int> cnt(DG_VARP_MAXN + 1, 0);
   for (int64_t e = 0; e < E; ++e) ++cnt[v->deg[e] + 1];
   int pos = 0;
@@ -231,7 +239,17 @@ dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double
   }
   v->list.resize(E);
   std::vector<int> fill(v->first, v->first + DG_VARP_MAXN + 1);
-  for (int64_t e = 0; e < E; ++e) v->list[fill[v->deg[e] + 1]++] = (int)e;
+  {
+    const int px = std::min(kPencilX, nx), pz = std::min(kPencilZ, nz);
+    for (int zs = 0; zs < nz; zs += pz)
+      for (int xs = 0; xs < nx; xs += px)
+        for (int y = 0; y < ny; ++y)
+          for (int z = zs; z < std::min(zs + pz, nz); ++z)
+            for (int x = xs; x < std::min(xs + px, nx); ++x) {
+              const int64_t e = ((int64_t)z * ny + y) * nx + x;
+              v->list[fill[v->deg[e] + 1]++] = (int)e;
+            }
+  }
   // per-degree tables (the single-degree library's), Gauss-Legendre rules
   double xi[DG_VARP_MAXN + 1][DG_MAXN], w[DG_VARP_MAXN + 1][DG_MAXN];
   DGVarpTabs& H = *v->htabs;
