@@ -20,8 +20,12 @@
 //   is exactly the standard weak form.
 //
 // One workgroup per element, one thread per node (the pairwise fluxes make
-// the volume term O(N^4) per element, about 9N + 6 two-point fluxes per
-// node).  MODE 0: R = dQ/dt.  MODE 1: LSERK45 stage, Qout = Qin + b res
+// the volume term O(N^4) per element).  The last two terms of B_f depend on
+// the face point only, not on the node along the line: they are formed once
+// per face point in the face phase, so a node evaluates N + 2 two-point
+// fluxes per direction and each face point N (3N + 6 per node and 6 per
+// node for the faces, against 9N + 6 when every node forms all of B_f).
+// MODE 0: R = dQ/dt.  MODE 1: LSERK45 stage, Qout = Qin + b res
 // with res = a res + dt R in place (Qin and Qout differ: neighbours read
 // Qin).  MODE 2: the first stage (res = dt R without reading res).
 
@@ -97,11 +101,13 @@ __device__ __forceinline__ Prim lds_tprim(const double (*T)[SCfg<N>::N2], int pt
 
 // Volume and face terms of direction D for node (m0 along the line, pt
 // across it) of the element whose node primitives are P, accumulated (with
-// the -(2/h_D) factor) into out.
+// the -(2/h_D) factor) into out.  G holds, per face point, the part of the
+// face term that does not depend on the node along the line:
+// F*_f - sum_a l_a(f) f_S(Q~_f, Q_a).
 template <int N, int D>
 __device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)[SCfg<N>::N3],
                                            const double (*Dm)[N], const double (*Tp)[6][SCfg<N>::N2],
-                                           const double (*Fs)[5][SCfg<N>::N2], int m0, int pt, double* out) {
+                                           const double (*G)[5][SCfg<N>::N2], int m0, int pt, double* out) {
   const Prim si = lds_prim<N>(P, dgdev::tnode<N>(D, m0, pt));
   double vol[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum_a 2 D_ia f_S(Q_i, Q_a)
   double em[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(-1) f_S(Q_i, Q_a)
@@ -124,14 +130,8 @@ __device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)
     const Prim tf = lds_tprim<N>(Tp[2 * D + s], pt);
     double fi[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     kg_acc<D>(si, tf, 1.0, fi);                  // f_S(Q_i, Q~_f)
-    double sf[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(f) f_S(Q~_f, Q_a)
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
-      const Prim sa = lds_prim<N>(P, dgdev::tnode<N>(D, a, pt));
-      kg_acc<D>(tf, sa, s ? tb.lp[a] : tb.lm[a], sf);
-    }
-#pragma unroll
-    for (int v = 0; v < 5; ++v) br[s][v] = fi[v] - (s ? ep[v] : em[v]) + Fs[2 * D + s][v][pt] - sf[v];
+    for (int v = 0; v < 5; ++v) br[s][v] = fi[v] - (s ? ep[v] : em[v]) + G[2 * D + s][v][pt];
   }
   const double sc = tb.sc[D];
 #pragma unroll
@@ -139,14 +139,26 @@ __device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)
     out[v] -= sc * (vol[v] + tb.liftp[m0] * br[1][v] - tb.liftm[m0] * br[0][v]);
 }
 
+// sum_a l_a(f) f_S(Q~_f, Q_a) along the D-line through face point pt
+// (weights c = l(-1) or l(+1) of the face's side).
+template <int N, int D>
+__device__ __forceinline__ void face_line_sum(const double (*P)[SCfg<N>::N3], const Prim& tf, const double* c,
+                                              int pt, double* sf) {
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const Prim sa = lds_prim<N>(P, dgdev::tnode<N>(D, a, pt));
+    kg_acc<D>(tf, sa, c[a], sf);
+  }
+}
+
 template <int N, int MODE>
-__global__ void __launch_bounds__(SCfg<N>::NT)
+__global__ void __launch_bounds__(SCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR, double a,
         double b, double dt) {
   constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3, NT = SCfg<N>::NT;
   __shared__ double P[6][N3];        // node primitives
   __shared__ double Tp[6][6][N2];    // own trace primitives per face (2d + side)
-  __shared__ double Fs[6][5][N2];    // Lax-Friedrichs flux per face point
+  __shared__ double G[6][5][N2];     // per face point: Lax-Friedrichs flux - sum_a l_a f_S(Q~_f, Q_a)
   __shared__ double Dm[N][N];        // D_ia = l_a'(xi_i)
   const int e = blockIdx.x;
   const int t = threadIdx.x;
@@ -169,6 +181,7 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
     P[4][t] = s.p;
     P[5][t] = s.e;
   }
+  __syncthreads();   // the face phase reads the node primitives
   for (int fp = t; fp < 6 * N2; fp += NT) {
     const int face = fp / N2, pt = fp % N2, d = face >> 1, s = face & 1;
     const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
@@ -190,8 +203,13 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
     else if (d == 1) s ? dgdev::lf_flux_d<1>(own, nbr, tb.gamma, tb.gm1, fl) : dgdev::lf_flux_d<1>(nbr, own, tb.gamma, tb.gm1, fl);
     else s ? dgdev::lf_flux_d<2>(own, nbr, tb.gamma, tb.gm1, fl) : dgdev::lf_flux_d<2>(nbr, own, tb.gamma, tb.gm1, fl);
     const Prim so = to_prim(own, tb.gm1);
+    double sf[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const double* c = s ? tb.lp : tb.lm;
+    if (d == 0) face_line_sum<N, 0>(P, so, c, pt, sf);
+    else if (d == 1) face_line_sum<N, 1>(P, so, c, pt, sf);
+    else face_line_sum<N, 2>(P, so, c, pt, sf);
 #pragma unroll
-    for (int f = 0; f < 5; ++f) Fs[face][f][pt] = fl[f];
+    for (int f = 0; f < 5; ++f) G[face][f][pt] = fl[f] - sf[f];
     Tp[face][0][pt] = so.r;
     Tp[face][1][pt] = so.u[0];
     Tp[face][2][pt] = so.u[1];
@@ -203,9 +221,9 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
   if (t >= N3) return;
   const int i = t % N, j = (t / N) % N, k = t / N2;
   double rate[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  split_line<N, 0>(tb, P, Dm, Tp, Fs, i, j + N * k, rate);
-  split_line<N, 1>(tb, P, Dm, Tp, Fs, j, i + N * k, rate);
-  split_line<N, 2>(tb, P, Dm, Tp, Fs, k, i + N * j, rate);
+  split_line<N, 0>(tb, P, Dm, Tp, G, i, j + N * k, rate);
+  split_line<N, 1>(tb, P, Dm, Tp, G, j, i + N * k, rate);
+  split_line<N, 2>(tb, P, Dm, Tp, G, k, i + N * j, rate);
   const int64_t g = (int64_t)e * N3 + t;
   if (MODE == 0) {
 #pragma unroll
