@@ -38,7 +38,24 @@ struct VCfg {
   static constexpr int N2 = N * N;
   static constexpr int N3 = N * N * N;
   static constexpr int NT = N3 <= 64 ? 64 : (N3 + 63) / 64 * 64;
+  static constexpr int NW = NT / 64;
+  // face phase: LPF lanes per face, FPW faces per wave (the two faces of
+  // one direction share a wave when a face fits half a wave, so the
+  // direction is uniform over the wave and static inside the loads),
+  // NSLOT wave-sized slots per element
+  static constexpr int LPF = N2 <= 32 ? 32 : 64;
+  static constexpr int FPW = 64 / LPF;
+  static constexpr int NSLOT = 6 / FPW;
 };
+
+// Face and tangential point of lane `lane` in face slot `s`; false for the
+// lanes past the face's points.
+template <int N>
+__device__ __forceinline__ bool face_lane(int s, int lane, int& face, int& pt) {
+  face = s * VCfg<N>::FPW + lane / VCfg<N>::LPF;
+  pt = lane % VCfg<N>::LPF;
+  return pt < VCfg<N>::N2;
+}
 
 // (u, v, w, T) of a conserved state, T = p / rho with Eq. (3)'s pressure.
 __device__ __forceinline__ void primitive(const double* q, double gm1, double* P) {
@@ -78,6 +95,43 @@ __device__ __forceinline__ double br1_line(const DGTables& tb, const double* X, 
   return tb.sc[d] * (tb.liftp[m0] * hat_p - tb.liftm[m0] * hat_m - vol);
 }
 
+// A neighbour's primitive trace on our face point pt of direction D: its
+// -D face (s = 1, our +D face) or its +D face (s = 0), from its state at q
+// (field stride fs), summed over its normal line.
+template <int N, int D>
+__device__ __forceinline__ void prim_trace(const DGTables& tb, const double* __restrict__ q, int64_t fs, int s,
+                                           int pt, double* acc) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int node = dgdev::tnode<N>(D, m, pt);
+    double v[5], p[4];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) v[f] = q[f * fs + node];
+    primitive(v, tb.gm1, p);
+    const double wgt = s ? tb.lm[m] : tb.lp[m];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = fma(wgt, p[c], acc[c]);
+  }
+}
+
+// A neighbour's trace of its direction-D viscous flux (4 values) on our
+// face point pt, as prim_trace.
+template <int N, int D>
+__device__ __forceinline__ void flux_trace(const DGTables& tb, const double* __restrict__ fv, int64_t fs, int s,
+                                           int pt, double* acc) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int node = dgdev::tnode<N>(D, m, pt);
+    const double wgt = s ? tb.lm[m] : tb.lp[m];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = fma(wgt, fv[(D * 4 + c) * fs + node], acc[c]);
+  }
+}
+
 template <int N>
 __global__ void __launch_bounds__(VCfg<N>::NT)
 k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, double mu, double kappa) {
@@ -95,22 +149,21 @@ k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, 
 #pragma unroll
     for (int c = 0; c < 4; ++c) P[c][t] = p[c];
   }
-  for (int fp = t; fp < 6 * N2; fp += NT) {
-    const int face = fp / N2, pt = fp % N2, d = face >> 1, s = face & 1;
-    const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int m = 0; m < N; ++m) {
-      const int64_t g = (int64_t)en * N3 + dgdev::tnode<N>(d, m, pt);
-      double q[5], p[4];
+  const int wave = t >> 6, lane = t & 63;
+  for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
+    int face, pt;
+    if (face_lane<N>(sl, lane, face, pt)) {
+      const int s = face & 1;
+      const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, face >> 1, s ? 1 : -1);
+      double acc[4];
+      switch (face >> 1) {   // uniform over the wave
+        case 0: prim_trace<N, 0>(tb, Q + (int64_t)en * N3, fs, s, pt, acc); break;
+        case 1: prim_trace<N, 1>(tb, Q + (int64_t)en * N3, fs, s, pt, acc); break;
+        default: prim_trace<N, 2>(tb, Q + (int64_t)en * N3, fs, s, pt, acc); break;
+      }
 #pragma unroll
-      for (int f = 0; f < 5; ++f) q[f] = Q[f * fs + g];
-      primitive(q, tb.gm1, p);
-      const double wgt = s ? tb.lm[m] : tb.lp[m];   // the +d neighbour's -d face, the -d neighbour's +d face
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = fma(wgt, p[c], acc[c]);
+      for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
   }
   __syncthreads();
   if (t >= N3) return;
@@ -159,18 +212,21 @@ k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R,
 #pragma unroll
     for (int c = 0; c < 12; ++c) F[c][t] = Fv[c * fs + (int64_t)e * N3 + t];
   }
-  for (int fp = t; fp < 6 * N2; fp += NT) {
-    const int face = fp / N2, pt = fp % N2, d = face >> 1, s = face & 1;
-    const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int m = 0; m < N; ++m) {
-      const int64_t g = (int64_t)en * N3 + dgdev::tnode<N>(d, m, pt);
-      const double wgt = s ? tb.lm[m] : tb.lp[m];
+  const int wave = t >> 6, lane = t & 63;
+  for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
+    int face, pt;
+    if (face_lane<N>(sl, lane, face, pt)) {
+      const int s = face & 1;
+      const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, face >> 1, s ? 1 : -1);
+      double acc[4];
+      switch (face >> 1) {   // uniform over the wave
+        case 0: flux_trace<N, 0>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
+        case 1: flux_trace<N, 1>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
+        default: flux_trace<N, 2>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
+      }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = fma(wgt, Fv[(d * 4 + c) * fs + g], acc[c]);
+      for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
   }
   __syncthreads();
   if (t >= N3) return;
