@@ -92,9 +92,13 @@ def _copy_tree(dst):
                     ignore=shutil.ignore_patterns("*.npz", "__pycache__"))
 
 
-def _run_pins(dst):
+def _run_pins(dst, first=None):
+    """All pins, stopping at the first failure; the mutated module's own
+    pin file (test_oracle_<module>.py) first, so that a caught mistake
+    stops early."""
+    order = sorted(PIN_TESTS, key=lambda f: f != first)
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"] + \
-          [os.path.join("tests", f) for f in PIN_TESTS]
+          [os.path.join("tests", f) for f in order]
     env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1", OMP_NUM_THREADS="2", OPENBLAS_NUM_THREADS="2")
     return subprocess.run(cmd, cwd=dst, capture_output=True, text=True, timeout=600, env=env)
 
@@ -102,13 +106,15 @@ def _run_pins(dst):
 def _case(tmp, k, mutation):
     dst = os.path.join(tmp, f"case{k}")
     _copy_tree(dst)
+    first = None
     if mutation is not None:
         fname, old, new, _ = mutation
         path = os.path.join(dst, "oracle", fname)
         src = open(path).read()
         assert src.count(old) == 1, f"mutation anchor not found once in {fname}: {old!r}"
         open(path, "w").write(src.replace(old, new))
-    return _run_pins(dst)
+        first = "test_oracle_" + fname
+    return _run_pins(dst, first)
 
 
 @pytest.mark.slow
