@@ -3,7 +3,7 @@
 library, mixed degrees 0..7 on ragged meshes element by element, three
 LSERK45 steps, conservation, the 48^3 Taylor-Green workload with
 enstrophy-driven degrees 3..5 on sampled elements (3x3x3 periodic
-patches), and the argument checks."""
+patches), meshes one or two elements across, and the argument checks."""
 
 import numpy as np
 import pytest
@@ -213,3 +213,24 @@ def test_argument_checks(dgm):
     ws = torch.empty(256, dtype=torch.uint8, device="cuda")
     with pytest.raises(dgm.DGError, match="workspace"):
         dgm.dg_varp_set_workspace(v.v, ws)
+
+
+@pytest.mark.parametrize("n,deg", [((1, 1, 1), [3]), ((2, 1, 1), [1, 3]), ((1, 2, 1), [4, 0]),
+                                   ((1, 1, 2), [2, 5]), ((2, 2, 1), [0, 1, 2, 3]), ((3, 1, 1), [7, 1, 4])])
+def test_degenerate_meshes_vs_oracle(dgm, n, deg):
+    """Meshes one or two elements across: an element is its own neighbour
+    (1 x 1 x 1), or two distinct faces join the same pair of elements of
+    different degrees (the + and - faces along a direction of length 2)."""
+    L = (0.7, 1.1, 0.9)
+    deg3 = np.array(deg).reshape(n[2], n[1], n[0])
+    print(f"[varp degenerate n={n} degrees {deg}]", flush=True)
+    Q = W.varp_state(n, deg3, _smooth, L=L)
+    ora = VariableDegreeDG(n, deg3, L=L)
+    v = dgm.VariableDegree(n, deg3, L=L)
+    Rg = _host(v.rhs(_dev(Q)))
+    Ro = ora.rhs(Q)
+    err = _err(ora, Q, Rg, Ro)
+    print("scaled error per field", err)
+    assert np.all(err <= TOL), err
+    tot = ora.integrals(Rg)
+    assert np.all(np.abs(tot) <= 1e-13 * ora.integrals(np.abs(Rg)))
