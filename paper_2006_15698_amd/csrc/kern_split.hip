@@ -38,7 +38,9 @@ template <int N>
 struct SCfg {
   static constexpr int N2 = N * N;
   static constexpr int N3 = N * N * N;
-  static constexpr int NT = N3 <= 64 ? 64 : (N3 + 63) / 64 * 64;
+  // whole waves covering the nodes and the 6 N^2 face points (the face
+  // phase in one round)
+  static constexpr int NT = (N3 > 6 * N2 ? N3 : 6 * N2) <= 64 ? 64 : ((N3 > 6 * N2 ? N3 : 6 * N2) + 63) / 64 * 64;
 };
 
 // Primitive description of a state: rho, u, v, w, p, e = E / rho.
