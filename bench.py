@@ -392,6 +392,17 @@ def run_batch(args):
     degs = {}
     for sp in specs:
         degs[sp["p"]] = degs.get(sp["p"], 0) + 1
+    # the other launch form (one persistent launch per stage, or one launch
+    # per degree) on the same state and steps; its results are bitwise the same
+    opts = b.options()
+    other = dg.DG_BATCH_PERSISTENT if opts["batch_launch"] == dg.DG_BATCH_PER_DEGREE else dg.DG_BATCH_PER_DEGREE
+    b.set_option(dg.DG_OPT_BATCH_LAUNCH, other)
+    b.step(Q, res, nsteps=1, graph=True)
+    torch.cuda.synchronize()
+    ms_other = timed(K)
+    b.set_option(dg.DG_OPT_BATCH_LAUNCH, opts["batch_launch"])
+    form_name = {dg.DG_BATCH_PERSISTENT: "one persistent launch per RK stage (k_batch_stage)",
+                 dg.DG_BATCH_PER_DEGREE: "one launch per degree and RK stage (k_batch_degree)"}
     return {
         "metric": "GDOF-RK-stages/sec", "value": value, "unit": "GDOF-RK-stages/sec", "n_gpus": 1,
         "steps": K, "warmup": args.warmup, "ms_per_step": ms / K, "higher_is_better": True,
@@ -412,6 +423,8 @@ def run_batch(args):
                                 if b.options()["batch_launch"] == dg.DG_BATCH_PER_DEGREE
                                 else "k_batch_stage (persistent, all meshes)"), "avg_launch_us": avg_s * 1e6,
                      "alg_bytes_per_launch": ALG_BYTES_PER_DOF_STAGE * dof},
+        "other_launch_form": {"form": form_name[other], "ms_per_step": ms_other / K,
+                              "value": dof * 5 * K / (ms_other * 1e-3) / 1e9},
     }
 
 
