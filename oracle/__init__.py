@@ -40,6 +40,11 @@ Parity status per function (each pin lives in ``tests/test_oracle_*.py``):
                                  conservation across degree jumps, rate
                                  convergence with mixed degrees, axis
                                  permutation equivariance)
+  hp.RefinedMeshDG               pinned (no refinement is varp, all cells
+                                 refined is dg.DG on the twice finer mesh,
+                                 face coverage, free stream and conservation
+                                 across hanging faces, rate convergence with
+                                 half the cells refined)
 """
 
-from . import quadrature, euler, dg, lserk, viscous, splitform, varp  # noqa: F401
+from . import quadrature, euler, dg, lserk, viscous, splitform, varp, hp  # noqa: F401

@@ -18,7 +18,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["test_oracle_quadrature.py", "test_oracle_euler.py", "test_oracle_dg.py", "test_oracle_lserk.py",
-             "test_oracle_adjoint.py", "test_oracle_viscous.py", "test_oracle_splitform.py", "test_oracle_varp.py"]
+             "test_oracle_adjoint.py", "test_oracle_viscous.py", "test_oracle_splitform.py", "test_oracle_varp.py",
+             "test_oracle_hp.py"]
 
 # (oracle file, exact text, replacement, what the mistake is)
 MUTATIONS = [
@@ -75,6 +76,15 @@ MUTATIONS = [
     ("varp.py", "wf, Bm_own = self._mortar(d, 1, p, m)", "wf, Bm_own = self._mortar(d, -1, p, m)",
      "own trace taken on the wrong face"),
     ("varp.py", "return w[lo] * w[hi], basis3d", "return w[lo] * w[lo], basis3d", "mortar weights of one axis twice"),
+    ("hp.py", "small = a if self.size[a][t[0]] <= self.size[b][t[0]] else b",
+     "small = a if self.size[a][t[0]] >= self.size[b][t[0]] else b", "mortar on the larger face"),
+    ("hp.py", "ra[:, d], rb[:, d] = 1.0, -1.0", "ra[:, d], rb[:, d] = 1.0, 1.0", "neighbour's trace on its far face"),
+    ("hp.py", "kk[t[0]], kk[t[1]] = k1, k2", "kk[t[0]], kk[t[1]] = k1, k1", "one quarter of a hanging face twice"),
+    ("hp.py", "S[:, self.off[b]:self.off[b + 1]] -= fstar @ Bb", "S[:, self.off[b]:self.off[b + 1]] += fstar @ Bb",
+     "sign of the neighbour's face term"),
+    ("hp.py", "area = self.size[small][t[0]] * self.size[small][t[1]] / 4.0",
+     "area = self.hc[t[0]] * self.hc[t[1]] / 4.0", "the cell's face area for every sub-face"),
+    ("hp.py", "                    kk[d] = 0\n", "                    kk[d] = 1\n", "wrong child across a cell face"),
 ]
 
 

@@ -298,3 +298,47 @@ def tgv_degrees(n, pmin=3, pmax=5, L=(2 * np.pi, 2 * np.pi, 2 * np.pi)):
     w3 = 2 * np.sin(X) * np.sin(Y) * np.cos(Z)
     s = np.sqrt(w1 ** 2 + w2 ** 2 + w3 ** 2) / 2.0
     return (pmin + np.rint((pmax - pmin) * s)).astype(np.int64)
+
+
+def hp_elements(n, refine, L=(1.0, 1.0, 1.0)):
+    """Elements of a periodic base mesh whose cells refine[cz, cy, cx] = 1 are
+    split once into 2 x 2 x 2 children: a list, in element order (cells
+    c = (cz ny + cy) nx + cx ascending, a refined cell's children (kz, ky, kx)
+    with kx fastest), of (origin [3], size [3], level)."""
+    nx, ny, nz = _mesh(n)
+    ref = np.asarray(refine, dtype=int).reshape(nz, ny, nx)
+    h = np.array([L[0] / nx, L[1] / ny, L[2] / nz])
+    out = []
+    for cz in range(nz):
+        for cy in range(ny):
+            for cx in range(nx):
+                base = np.array([cx, cy, cz]) * h
+                if ref[cz, cy, cx]:
+                    for kz in range(2):
+                        for ky in range(2):
+                            for kx in range(2):
+                                out.append((base + np.array([kx, ky, kz]) * h / 2, h / 2, 1))
+                else:
+                    out.append((base, h, 0))
+    return out
+
+
+def hp_state(n, refine, degrees, primitive, L=(1.0, 1.0, 1.0), gamma=GAMMA):
+    """State [5, total nodes] of a refined mesh (hp_elements) with one degree
+    per element (element order) from primitive(X, Y, Z) -> (rho, u, v, w, p)."""
+    deg = np.asarray(degrees, dtype=np.int64).reshape(-1)
+    blocks = []
+    for (x0, h, _), p in zip(hp_elements(n, refine, L), deg):
+        xi = _gl_nodes(int(p))
+        K, J, I = np.meshgrid(xi, xi, xi, indexing="ij")
+        X = x0[0] + (I + 1.0) * (h[0] / 2.0)
+        Y = x0[1] + (J + 1.0) * (h[1] / 2.0)
+        Z = x0[2] + (K + 1.0) * (h[2] / 2.0)
+        blocks.append(conserved(*primitive(X, Y, Z), gamma=gamma).reshape(5, -1))
+    return np.ascontiguousarray(np.concatenate(blocks, axis=1))
+
+
+def random_refinement(n, fraction, seed):
+    """Seeded refine[cz, cy, cx]: each cell refined with the given probability."""
+    nx, ny, nz = _mesh(n)
+    return (np.random.default_rng(seed).random((nz, ny, nx)) < fraction).astype(np.int64)
