@@ -49,6 +49,12 @@ WORKLOADS = {
                                  "element, 3..5 from the initial enstrophy density (p = 3 + round(|curl u|), "
                                  "22/72/5% of the elements, 6% of the faces between two degrees), mortar faces "
                                  "between degrees, dt from CFL 0.3 at the highest degree, 50 LSERK45 steps"),
+    "tgv40_hp": (40, None, 50, "Taylor-Green vortex, [0,2pi]^3, Mach 0.1, 40^3 cells, the cells of initial "
+                               "enstrophy indicator |curl u|/2 >= 0.7 refined once into 2x2x2 children (7.8% of "
+                               "the cells, 98944 elements), degrees 3..5 from the indicator (children take their "
+                               "cell's), 14.0 M nodes, mortar faces between degrees and hanging faces between "
+                               "sizes, dt from CFL 0.3 at the highest degree and smallest element, 50 LSERK45 "
+                               "steps"),
     "batch512": (None, None, 20, "512 independent periodic meshes from seed 15698: density waves on "
                                  "[0,1]^3 and TGVs on [0,2pi]^3, n^3 elements with n uniform in 6..24, "
                                  "p uniform in 1..5, amplitudes uniform in [0.05,0.3], each mesh with "
@@ -94,6 +100,7 @@ STAGE_SOURCES = {
     "visc": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_visc.hip"],
     "split": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/kern_split.hip"],
     "varp": _COMMON_SOURCES + ["paper_2006_15698_amd/csrc/dg_varp.h", "paper_2006_15698_amd/csrc/kern_varp.hip",
+                               "paper_2006_15698_amd/csrc/kern_varp_hang.hip",
                                "paper_2006_15698_amd/csrc/varp_api.cpp"],
 }
 
@@ -479,6 +486,173 @@ def varp_cpu_baseline(deg, h, budget_s, m=8):
                       f"({dof} nodes) in {el:.1f} s; BLAS threads {threads}, host cpu_count {os.cpu_count()}"}
 
 
+def varp_roofline(v, Q, res, dt, K, nodes, faces, workload):
+    """Per-launch HIP events on the library's stream over a second pass of
+    the same K steps: every kernel's average launch and, for the stage
+    kernels, the algorithmic rate (160 B per node and stage, 120 in the
+    first stage).  The dominant kernel is the stage kernel of the degree
+    with the most nodes, stages 2..5 (its launches over both element sizes
+    where the mesh has refined cells).  nodes: {degree: nodes}; faces:
+    {"mortar": count, "hanging": count}."""
+    v.set_timing(1)
+    v.step(Q, res, dt, nsteps=K)
+    t = v.timing_read()
+    v.set_timing(0)
+    kernels = {}
+
+    def label(p, mode):
+        return f"k_varp p={p} {'stages 2..5' if mode == 1 else 'first stage'}"
+    for key, (k_ms, k_n) in t.items():
+        a_s = k_ms / k_n * 1e-3
+        if key in ("mortar", "hanging"):
+            kernels[f"k_varp_{key}"] = {"avg_launch_us": a_s * 1e6, "launches": k_n, "faces": faces.get(key)}
+            continue
+        p, mode = key
+        per = ALG_BYTES_PER_DOF_STAGE if mode == 1 else ALG_BYTES_PER_DOF_FIRST_STAGE
+        stages = 4 * K if mode == 1 else K
+        total = per * nodes[p] * stages
+        kernels[label(p, mode)] = {"avg_launch_us": a_s * 1e6, "launches": k_n,
+                                   "alg_bytes_per_launch": total / k_n, "achieved": total / (k_ms * 1e-3) / 1e9}
+    pdom = max(nodes, key=nodes.get)
+    dom = kernels[label(pdom, 1)]
+    return {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dom["achieved"] / HBM_PEAK_GBS,
+            "traffic": measured_traffic(workload, "varp", {}),
+            "kernel": f"k_varp<{pdom + 1}> (degree {pdom}: fused RHS + LSERK45 stage, stages 2..5)",
+            "avg_launch_us": dom["avg_launch_us"], "launches": dom["launches"],
+            "alg_bytes_per_launch": dom["alg_bytes_per_launch"], "kernels": kernels,
+            "stage_bytes_per_node": ALG_BYTES_PER_DOF_STAGE}
+
+
+def hp_cpu_baseline(ref, deg, h, budget_s, m=6):
+    """The refined-mesh oracle advancing RK stages on the host for about
+    ``budget_s`` seconds on an m^3-cell periodic block of the same cell size
+    carrying the refinement and degrees of the m^3 block of the mesh
+    (corners on a 2-cell lattice) whose share of nodes per (degree, size)
+    is closest to the whole mesh's."""
+    import numpy as np
+    import workloads as W
+    from oracle import lserk
+    from oracle.hp import RefinedMeshDG
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    n = ref.shape
+    cfirst = np.concatenate([[0], np.cumsum(np.where(ref.reshape(-1) == 1, 8, 1))])
+
+    def elements(cz, cy, cx):
+        c = (cz * n[1] + cy) * n[2] + cx
+        return deg[cfirst[c]:cfirst[c + 1]]
+
+    def node_share(r, d):
+        # nodes per (degree, level) over cells with refinement r and element degrees d
+        c = np.zeros(16)
+        lev = np.repeat(r.reshape(-1), np.where(r.reshape(-1) == 1, 8, 1))
+        np.add.at(c, d * 2 + lev, (d + 1) ** 3)
+        return c / c.sum()
+    want = node_share(ref, deg)
+    best = None
+    for oz in range(0, n[0] - m + 1, 2):
+        for oy in range(0, n[1] - m + 1, 2):
+            for ox in range(0, n[2] - m + 1, 2):
+                r = ref[oz:oz + m, oy:oy + m, ox:ox + m]
+                d = np.concatenate([elements(oz + k, oy + j, ox + i) for k in range(m) for j in range(m)
+                                    for i in range(m)])
+                gap = float(np.abs(node_share(r, d) - want).sum())
+                if best is None or gap < best[0]:
+                    best = (gap, np.ascontiguousarray(r), d)
+    _, rm, dm = best
+    Lm = tuple(float(hd) * m for hd in h)
+    ora = RefinedMeshDG((m, m, m), rm, dm, L=Lm)
+    Q = W.hp_state((m, m, m), rm, dm, W.tgv_primitives, L=Lm)
+    res = np.zeros_like(Q)
+    dt = ora.dt_cfl(Q, 0.3)
+    t0 = time.perf_counter()
+    stages = 0
+    while True:
+        lserk.stage(stages % 5, Q, res, dt, ora.rhs)
+        stages += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    dof = ora.num_dof()
+    return {"value": dof * stages / el / 1e9, "unit": "GDOF-RK-stages/s", "cores": threads, "kind": "oracle",
+            "sample": f"a {m}^3-cell block of the same cell size with the refinement and degrees of the mesh block "
+                      f"closest to its node share per (degree, element size) ({int(rm.sum())} cells refined, "
+                      f"{ora.E} elements, degrees {np.bincount(dm).tolist()}): {stages} RK stages ({dof} nodes) "
+                      f"in {el:.1f} s; BLAS threads {threads}, host cpu_count {os.cpu_count()}"}
+
+
+def run_hp(args):
+    """The refined-mesh configuration: per stage the launches of the faces
+    between degrees and of the hanging faces, then one fused stage launch
+    per (degree, element size)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2006_15698_amd import dg
+
+    n, _, cfg_steps, desc = WORKLOADS["tgv40_hp"]
+    K = cfg_steps if args.steps is None else args.steps
+    L = (2 * math.pi,) * 3
+    ref, deg = W.tgv_refined_mesh((n, n, n))
+    v = dg.VariableDegree((n, n, n), deg, L=L, refine=ref)
+    Qh = W.hp_state((n, n, n), ref, deg, W.tgv_primitives, L=L)
+    # dt = CFL / ((2 p_max + 1) max over nodes of sum_d (|u_d| + c) / h_d),
+    # h the node's element size
+    _, size, _ = W.hp_geometry((n, n, n), ref, L)
+    hn = np.repeat(size, (deg + 1) ** 3, axis=0)
+    rho = Qh[0]
+    vel = Qh[1:4] / rho
+    c = np.sqrt(W.GAMMA * (W.GAMMA - 1) * (Qh[4] - 0.5 * rho * (vel ** 2).sum(axis=0)) / rho)
+    rate = float(np.max(sum((np.abs(vel[d]) + c) / hn[:, d] for d in range(3))))
+    dt = 0.3 / ((2 * int(deg.max()) + 1) * rate)
+    Q0 = torch.from_numpy(Qh.reshape(-1)).cuda()
+    dof = v.num_dof()
+    Q = Q0.clone()
+    res = torch.zeros_like(Q)
+    if args.warmup > 0:
+        v.step(Q, res, dt, nsteps=args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    v.step(Q, res, dt, nsteps=K)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    value = dof * 5 * K / (ms * 1e-3) / 1e9
+    counts = np.bincount(deg, minlength=8)
+    nodes = {int(p): int(counts[p]) * (p + 1) ** 3 for p in range(8) if counts[p]}
+    # faces: hanging sub-faces (4 per refined-unrefined cell pair), and
+    # same-size faces between degrees (whole cells, or 4 fine faces between
+    # two refined cells; siblings share their cell's degree)
+    cdeg = deg[np.concatenate([[0], np.cumsum(np.where(ref.reshape(-1) == 1, 8, 1))])[:-1]].reshape(ref.shape)
+    nhang = nmortar = 0
+    for ax in range(3):
+        rn, dn = np.roll(ref, -1, axis=ax), np.roll(cdeg, -1, axis=ax)
+        nhang += 4 * int(np.sum(ref != rn))
+        nmortar += int(np.sum((ref == 0) & (rn == 0) & (cdeg != dn))) + 4 * int(np.sum((ref == 1) & (rn == 1) &
+                                                                                    (cdeg != dn)))
+    out = {
+        "metric": "GDOF-RK-stages/sec", "value": value, "unit": "GDOF-RK-stages/sec", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": ms / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"tgv40_hp: {desc}", "cells": n ** 3, "refined_cells": int(ref.sum()),
+                   "elements": int(deg.size), "dof": dof, "dt": dt,
+                   "elements_per_degree": {int(p): int(counts[p]) for p in range(8) if counts[p]},
+                   "mortar_faces": nmortar, "hanging_subfaces": nhang, "precision": "fp64"},
+    }
+    if not args.no_roofline:
+        out["roofline"] = varp_roofline(v, Q, res, dt, K, nodes, {"mortar": nmortar, "hanging": nhang}, "tgv40_hp")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = hp_cpu_baseline(ref, deg, np.array(L) / n, args.cpu_seconds)
+    return out
+
+
 def run_varp(args):
     """The variable-degree configuration: per stage the mortar-face launch
     and one fused stage launch per degree."""
@@ -527,35 +701,7 @@ def run_varp(args):
                    "mortar_faces": nmortar, "precision": "fp64"},
     }
     if not args.no_roofline:
-        # Per-launch HIP events on the library's stream (a second pass over
-        # the same K steps); the dominant kernel is the stage kernel of the
-        # degree with the most nodes, stages 2..5.
-        v.set_timing(1)
-        v.step(Q, res, dt, nsteps=K)
-        t = v.timing_read()
-        v.set_timing(0)
-        kernels = {}
-
-        def label(p, mode):
-            return f"k_varp p={p} {'stages 2..5' if mode == 1 else 'first stage'}"
-        for key, (k_ms, k_n) in t.items():
-            a_s = k_ms / k_n * 1e-3
-            if key == "mortar":
-                kernels["k_varp_mortar"] = {"avg_launch_us": a_s * 1e6, "launches": k_n, "faces": nmortar}
-                continue
-            p, mode = key
-            per = ALG_BYTES_PER_DOF_STAGE if mode == 1 else ALG_BYTES_PER_DOF_FIRST_STAGE
-            kernels[label(p, mode)] = {"avg_launch_us": a_s * 1e6, "launches": k_n,
-                                       "alg_bytes_per_launch": per * nodes[p], "achieved": per * nodes[p] / a_s / 1e9}
-        pdom = max(nodes, key=nodes.get)
-        dom = kernels[label(pdom, 1)]
-        out["roofline"] = {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": dom["achieved"] / HBM_PEAK_GBS,
-                           "traffic": measured_traffic("tgv48_varp", "varp", {}),
-                           "kernel": f"k_varp<{pdom + 1}> (degree {pdom}: fused RHS + LSERK45 stage, stages 2..5)",
-                           "avg_launch_us": dom["avg_launch_us"], "launches": dom["launches"],
-                           "alg_bytes_per_launch": dom["alg_bytes_per_launch"], "kernels": kernels,
-                           "stage_bytes_per_node": ALG_BYTES_PER_DOF_STAGE}
+        out["roofline"] = varp_roofline(v, Q, res, dt, K, nodes, {"mortar": nmortar}, "tgv48_varp")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = varp_cpu_baseline(deg, h, args.cpu_seconds)
     return out
@@ -628,6 +774,9 @@ def main():
         return
     if args.workload == "tgv48_varp":
         print(json.dumps(run_varp(args)), flush=True)
+        return
+    if args.workload == "tgv40_hp":
+        print(json.dumps(run_hp(args)), flush=True)
         return
 
     n, p, cfg_steps, desc = WORKLOADS[args.workload]

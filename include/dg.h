@@ -367,39 +367,56 @@ int dg_batch_rk_steps(dg_batch* b, double* Q, double* res, int nsteps);
  * step parity; recaptured when the pointers change). */
 int dg_batch_graph_steps(dg_batch* b, double* Q, double* res, int nsteps);
 
-/* ---- Variable degree per element ------------------------------------------
+/* ---- Variable degree per element, optionally refined cells ---------------
  * The hp-adaptive setting that the paper names (Sections I and III: degree
- * adapted element by element) on the conforming periodic Cartesian mesh.
- * Every element e has its own degree p_e in 0..7 and the scheme of Section
- * II-B (Eq. (5), collocated Gauss-Legendre basis, local Lax-Friedrichs flux)
- * on it; a face between degrees p and q is integrated on a mortar, the
- * tensor Gauss-Legendre rule of max(p, q) + 1 points per tangential
- * direction, where both elements' traces are evaluated and the flux is
- * formed once for both sides (conservative; where p = q it is the
+ * and element size adapted element by element) on the periodic Cartesian
+ * mesh of nx x ny x nz cells, each cell one element or, refined once, eight
+ * elements of half its size.  Every element e has its own degree p_e in
+ * 0..7 and the scheme of Section II-B (Eq. (5), collocated Gauss-Legendre
+ * basis, local Lax-Friedrichs flux) on it.  A face whose two elements
+ * differ in degree or size is integrated on a mortar: the tensor
+ * Gauss-Legendre rule of max(p, q) + 1 points per tangential direction on
+ * the smaller of the two faces (where a refined cell meets an unrefined
+ * one, a fine element's face: a quarter of the coarse face, a hanging
+ * face), where both elements' traces are evaluated and the flux is formed
+ * once for both sides (conservative; where the two sides match it is the
  * single-degree scheme, bitwise).  Per RK stage one launch for the faces
- * between degrees (each face's flux projected onto both sides), then one
- * launch per degree present.
+ * between degrees, one for the hanging faces (each face's flux projected
+ * onto both sides), then one launch per (degree, element size) present.
+ * Elements are numbered cell by cell, c = (cz ny + cy) nx + cx; a refined
+ * cell's children in the order (kz, ky, kx), kx fastest (child (kx, ky, kz)
+ * spans [cx + kx/2, cx + (kx+1)/2] h_x, ...).
  * State layout: Q[f * T + off[e] + (k N_e + j) N_e + i], field f = rho, rho u,
  * rho v, rho w, rho E, T = dg_varp_num_dof, off[e] = dg_varp_offset(v, e):
- * the elements' [N_e]^3 blocks back to back, e = (ez ny + ey) nx + ex, the
- * node index i fastest.  Arrays are device pointers, FP64, 8-byte aligned;
- * Q must not overlap R or res (DG_EALIAS). */
+ * the elements' [N_e]^3 blocks back to back in element order, the node
+ * index i fastest.  Arrays are device pointers, FP64, 8-byte aligned; Q
+ * must not overlap R or res (DG_EALIAS). */
 typedef struct dg_varp dg_varp;
 
-/* nx, ny, nz >= 1; degrees[E] (HOST, element order as above) each in 0..7
+/* No refinement: E = nx ny nz elements, e = (ez ny + ey) nx + ex.
+ * nx, ny, nz >= 1; degrees[E] (HOST, element order as above) each in 0..7
  * (DG_EUNSUPPORTED otherwise); L[3] (HOST) the domain lengths.  NULL on
  * error (dg_last_error). */
 dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double* L, double gamma);
+/* refine[nx ny nz] (HOST, cell order) each 0 or 1 (DG_EINVAL otherwise):
+ * E = nx ny nz + 7 (number of refined cells) elements; degrees[E] (HOST,
+ * element order) each in 0..7; at most 2^31-1 elements, and where any
+ * cell is refined at most 2^31-1 cells of the twice finer mesh
+ * (DG_EUNSUPPORTED).  NULL on error. */
+dg_varp* dg_varp_create_refined(int nx, int ny, int nz, const int* refine, const int* degrees, const double* L,
+                                double gamma);
 void dg_varp_destroy(dg_varp* v);
 int dg_varp_set_stream(dg_varp* v, void* hip_stream);
 /* Total nodes T (the DOF count), -1 for NULL. */
 int64_t dg_varp_num_dof(const dg_varp* v);
+/* Number of elements E, -1 for NULL. */
+int64_t dg_varp_num_elements(const dg_varp* v);
 /* First node of element e (e = E gives T); -1 out of range. */
 int64_t dg_varp_offset(const dg_varp* v, int64_t e);
 size_t dg_varp_workspace_bytes(const dg_varp* v);
-/* Caller-owned device workspace (256-byte aligned): mortar tables, degrees,
- * offsets, element lists and the second state buffer of the ping-pong.
- * SYNCHRONISING (uploads the tables). */
+/* Caller-owned device workspace (256-byte aligned): mortar tables, face
+ * table, offsets, element lists, the face-flux buffer and the second state
+ * buffer of the ping-pong.  SYNCHRONISING (uploads the tables). */
 int dg_varp_set_workspace(dg_varp* v, void* dptr, size_t bytes);
 /* R = dQ/dt. */
 int dg_varp_rhs(dg_varp* v, const double* Q, double* R);
@@ -411,10 +428,13 @@ int dg_varp_rk_steps(dg_varp* v, double* Q, double* res, double dt, int nsteps);
 /* Not in the paper: measurement support.  While on, every launch is
  * bracketed by HIP events (switching on clears the record). */
 int dg_varp_set_timing(dg_varp* v, int on);
-/* SYNCHRONISING.  ms[3 p + mode], count[3 p + mode] (HOST arrays of 25):
- * summed milliseconds and launches of degree p's kernel, mode 0 right-hand
- * side, 1 RK stages 2..5, 2 the first RK stage; ms[24], count[24] the
- * mortar-face kernel.  Clears the record. */
+/* Slots of dg_varp_timing_read. */
+#define DG_VARP_TIMING_SLOTS 26
+/* SYNCHRONISING.  ms[3 p + mode], count[3 p + mode] (HOST arrays of
+ * DG_VARP_TIMING_SLOTS): summed milliseconds and launches of degree p's
+ * kernel (both element sizes), mode 0 right-hand side, 1 RK stages 2..5,
+ * 2 the first RK stage; ms[24], count[24] the kernel of the faces between
+ * degrees, ms[25], count[25] the hanging-face kernel.  Clears the record. */
 int dg_varp_timing_read(dg_varp* v, double* ms, int64_t* count);
 
 /* Not in the paper: measurement support.  Opt-in per-launch timing for

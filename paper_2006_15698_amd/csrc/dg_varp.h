@@ -23,39 +23,80 @@ struct DGVarpTabs {
   // weights times the basis, over the element's own face weights (the
   // surface integral on the mortar, lifted by the diagonal mass matrix)
   double proj[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][DG_VARP_MAXN * DG_VARP_MAXN];
+  // the same on one half of a coarse face (h = 0: xi in [-1, 0], h = 1:
+  // [0, 1]), at xi = (x^m_b + 2h - 1) / 2, for any m; the projection
+  // carries the half's factor 1/2 (a sub-face is a quarter of the coarse
+  // face: 1/2 per direction)
+  double hinterp[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][2][DG_VARP_MAXN * DG_VARP_MAXN];
+  double hproj[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][2][DG_VARP_MAXN * DG_VARP_MAXN];
 };
 
-// A face between elements of different degrees: element a (its +d face)
-// and its +d neighbour b (their -d face), with first nodes oa, ob; sa, sb
-// the first double of the two sides' projected fluxes ([5][N_a^2],
-// [5][N_b^2]) in the face-flux buffer.
+// A face between elements of the same size and different degrees: element
+// a (its +d face) and its +d neighbour b (their -d face), with first nodes
+// oa, ob; sa, sb the first double of the two sides' projected fluxes
+// ([5][N_a^2], [5][N_b^2]) in the face-flux buffer.
 struct DGVarpFace {
   int64_t oa, ob, sa, sb;
   int d;
   int code;            // (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (1 if a has the lower degree)
 };
 
+// A hanging sub-face: a quarter (q1, q2 along the two tangential axes in
+// increasing order) of a coarse element's face against a whole face of a
+// fine element.  oc, of: first nodes; sc: the coarse side's block for this
+// quarter ([5][N_c^2]), sf: the fine side's ([5][N_f^2]); cminus: the
+// coarse element is on the -d side (its +d face).
+struct DGVarpHang {
+  int64_t oc, of, sc, sf;
+  int d, nc, nf, q1, q2, cminus;
+};
+
+// What a face of an element takes its flux from: the low two bits of
+// DGVarpMesh::face, the rest (face >> 2) the place it names.
+enum {
+  DG_FACE_CONFORMING = 0,  // same size and degree: the neighbour's first node
+  DG_FACE_MORTAR = 1,      // the projected flux [5][N^2] in fbuf (a face between
+                           // degrees, or a fine element's face on a coarse one)
+  DG_FACE_HANGING = 2      // a coarse face on four fine ones: the first of the
+                           // quarters' blocks [4][5][N^2] in fbuf (q = 2 q2 + q1)
+};
+
 // Mesh description read by every launch.
 struct DGVarpMesh {
   const int64_t* off;      // first node of every element [E] (field stride T)
-  const int64_t* slot;     // [E][6]: a face's projected flux in fbuf, -1 where conforming
-  const int* list;         // elements grouped by degree, ascending inside a group
+  const int64_t* face;     // [E][6]: (place << 2) | DG_FACE_* of face 2d + side
+  const int* list;         // elements grouped by (degree, size), each group in visiting order
   const DGVarpTabs* tabs;
   const DGVarpFace* faces; // the mortar faces, grouped by code
-  double* fbuf;            // projected fluxes of the mortar faces
+  const DGVarpHang* hangs; // the hanging sub-faces, grouped by (nc, nf)
+  double* fbuf;            // projected fluxes of the mortar and hanging faces
   int64_t T;               // total nodes
-  int nx, ny, nz;
-  int nfaces;
+  int nfaces, nhangs;
 };
 
 // Launch one stage (mode 0: RR = dQ/dt; 1: LSERK45 stage Qin -> Qout with
-// res = RR in place; 2: the first stage) over the `count` elements of degree
-// N - 1 listed from list[first].  Reads the mortar fluxes that
-// dg_launch_varp_mortar wrote for the same Qin.
+// res = RR in place; 2: the first stage) over the `count` elements of N
+// points and one size listed from list[first] (tb: that size's tables).
+// Reads the mortar and hanging fluxes written for the same Qin.
 int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMesh& m, int first, int count,
                    const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt);
 // The flux of every mortar face of Qin, projected onto both sides' face
 // nodes, into m.fbuf.
 int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin);
+// The flux of every hanging sub-face of Qin, projected onto the fine
+// side's face nodes and the coarse side's quarter block, into m.fbuf.
+int dg_launch_varp_hanging(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin);
 // Elements per workgroup of the variable-degree kernel for N points.
 int dg_varp_epb(int N);
+
+namespace dgdev {
+// Node of a degree-(n-1) element: index m along direction d, tangential
+// point (a, b) (lower tangential axis a), as tnode with a runtime d.
+template <int NN>
+__device__ __forceinline__ int rt_node(int d, int m, int a, int b) {
+  if (d == 0) return m + NN * (a + NN * b);
+  if (d == 1) return a + NN * (m + NN * b);
+  return a + NN * (b + NN * m);
+}
+
+}  // namespace dgdev

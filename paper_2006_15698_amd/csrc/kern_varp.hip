@@ -1,42 +1,45 @@
-// Variable polynomial degree per element on the periodic Cartesian mesh:
-// per RK stage one mortar launch, then one fused RHS / LSERK45 stage launch
-// per degree present.
+// Variable polynomial degree per element, on the periodic Cartesian mesh
+// with cells optionally refined once into 2 x 2 x 2 children: per RK stage
+// one launch for the faces between degrees, one for the hanging faces, then
+// one fused RHS / LSERK45 stage launch per (degree, element size) present.
 //
-// The method of Section II-B on every element with its own degree (the
-// hp-adaptive setting that Sections I and III name), faces between elements
-// of degrees p and q integrated on a mortar: the Gauss-Legendre rule of
-// M = max(p, q) + 1 points per tangential direction, both traces evaluated
-// there, the local Lax-Friedrichs flux formed once, and the flux integrated
-// against each side's own test functions.  With the diagonal collocated
-// mass matrix divided out, the face term of a node is the one of Eq. (5) on
-// one element, with the face flux at the element's own face nodes replaced
-// by the projection
+// The method of Section II-B on every element with its own degree and size
+// (the hp-adaptive setting that Sections I and III name), every face whose
+// two sides differ integrated on a mortar: the Gauss-Legendre rule of
+// M = max(p, q) + 1 points per tangential direction on the smaller of the
+// two faces, both traces evaluated there, the local Lax-Friedrichs flux
+// formed once, and the flux integrated against each side's own test
+// functions.  With the diagonal collocated mass matrix divided out, the face
+// term of a node is the one of Eq. (5) on one element, with the face flux at
+// the element's own face nodes replaced by the projection
 //     G(t1, t2) = sum_{b1, b2} P[t1][b1] P[t2][b2] F*(b1, b2),
-//     P[t][b] = l_t(x^M_b) W^M_b / w_t,
-// which is F* itself on the side of higher degree (its face nodes are the
-// mortar points).
+//     P[t][b] = l_t(xi_b) W^M_b / w_t   (times 1/2 on a coarse face's half),
+// xi_b the mortar points in the element's own coordinate: x^M_b on a face
+// of the mortar's size (F* itself where the element's face nodes are the
+// mortar points), (x^M_b + 2h - 1) / 2 on half h of a coarse face; a coarse
+// face against four fine ones sums the four quarters' projections.
 //
-// k_varp_mortar: one wave per mortar face (faces grouped by degree pair):
-//   the lower-degree side's trace at its face nodes into LDS, the higher
-//   side's trace at its face nodes (the mortar points) in registers, the
-//   lower side's trace interpolated to the mortar points, the flux, written
-//   for the higher side and projected for the lower side into the face-flux
-//   buffer.
-// k_varp<N, MODE>: a workgroup owns EPB elements of one degree from the
-// degree's element list (in pencil order; each XCD takes a contiguous part),
-// one thread per node:
+// k_varp_mortar: one wave per face between degrees (same size; faces grouped
+//   by degree pair): the lower-degree side's trace at its face nodes into
+//   LDS, the higher side's trace at its face nodes (the mortar points) in
+//   registers, the lower side's trace interpolated to the mortar points, the
+//   flux, written for the higher side and projected for the lower side into
+//   the face-flux buffer.
+// k_varp_hanging (kern_varp_hang.hip): one wave per hanging sub-face.
+// k_varp<N, MODE>: a workgroup owns EPB elements of one degree and size from
+// that group's element list (in pencil order; each XCD takes a contiguous
+// part), one thread per node:
 //   A. the elements' states into LDS (each element's nodes are contiguous);
-//      one wave looks up the 6 EPB (face, element) tasks: the mortar flux's
-//      place in the buffer, or for a conforming face the neighbour's first
-//      node;
+//      one wave looks up the 6 EPB (face, element) tasks in the face table;
 //   B. one point per lane in 64-point slots of one face each: on a
 //      conforming face the neighbour's trace interpolated from its state
 //      along the normal line (global memory), the own trace from LDS and the
-//      flux (the chains of the single-degree kernel); on a mortar face the
-//      projected flux from the buffer;
+//      flux (the chains of the single-degree kernel); otherwise the
+//      projected flux from the buffer (the sum of the four quarters, in a
+//      fixed order, on a coarse face against fine ones);
 //   C/D. the volume contraction, lift and RK update of the single-degree
 //      neighbour-read kernel, in the same order, so that a mesh of one degree
-//      gives bitwise the results of that kernel.
+//      and size gives bitwise the results of that kernel.
 // State layout: Q[f * T + off[e] + (k N + j) N + i], T the total node count.
 
 #include "dg_varp.h"
@@ -59,15 +62,6 @@ struct VCfg {
   static constexpr int SMEM = 5 * NODES + 30 * FP + N * N + 2 * N;
   static_assert(TASKS <= 64, "the face tasks are looked up by one wave");
 };
-
-// Node of a degree-(n-1) element: index m along direction d, tangential
-// point (a, b) (lower tangential axis a), as tnode with a runtime d.
-template <int NN>
-__device__ __forceinline__ int rt_node(int d, int m, int a, int b) {
-  if (d == 0) return m + NN * (a + NN * b);
-  if (d == 1) return a + NN * (m + NN * b);
-  return a + NN * (b + NN * m);
-}
 
 // Flux at point pt of a conforming face (D, SIDE) of an element: the own
 // trace from LDS, the neighbour's from its state at qn (global memory),
@@ -233,8 +227,8 @@ __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_e
   constexpr int N2 = N * N, N3 = N2 * N, EPB = C::EPB, NODES = C::NODES, FP = C::FP;
   constexpr int TASKS = C::TASKS, WPF = C::WPF, NW = C::NW;
   __shared__ double smem[C::SMEM];
-  __shared__ long long sSrc[TASKS];   // conforming: the neighbour's first node; mortar: the flux's place
-  __shared__ int sMortar[TASKS];
+  __shared__ long long sSrc[TASKS];   // the place the face table names
+  __shared__ int sKind[TASKS];        // DG_FACE_*
   double* sQ = smem;               // [5][NODES] own states; reused as sF in C
   double* sF = smem;
   double* sH = sQ + 5 * NODES;     // [6][5][FP] face flux at the own face nodes
@@ -264,15 +258,15 @@ __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_e
     // task = face * EPB + element
     const int face = lane / EPB, fel = lane - face * EPB;
     long long src = 0;
-    int mortar = 0;
+    int kind = DG_FACE_CONFORMING;
     if (fel < ne) {
       const int e = mesh.list[first + blk0 + fel];
-      const long long sl = mesh.slot[(int64_t)e * 6 + face];
-      mortar = sl >= 0;
-      src = mortar ? sl : mesh.off[neighbour(mesh.nx, mesh.ny, mesh.nz, e, face >> 1, (face & 1) ? 1 : -1)];
+      const long long fr = mesh.face[(int64_t)e * 6 + face];
+      kind = (int)(fr & 3);
+      src = fr >> 2;
     }
     sSrc[lane] = src;
-    sMortar[lane] = mortar;
+    sKind[lane] = kind;
   }
   if (act) {
 #pragma unroll
@@ -313,10 +307,17 @@ __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_e
     if (i < FP && fel < ne) {
       const int task = face * EPB + fel;
       double fs[5];
-      if (sMortar[task]) {
+      const int kind = sKind[task];
+      if (kind == DG_FACE_MORTAR) {
         const double* h = mesh.fbuf + sSrc[task];
 #pragma unroll
         for (int f = 0; f < 5; ++f) fs[f] = h[f * N2 + pt];
+      } else if (kind == DG_FACE_HANGING) {
+        // the four quarters' projections, in the order q = 0..3
+        const double* h = mesh.fbuf + sSrc[task];
+#pragma unroll
+        for (int f = 0; f < 5; ++f)
+          fs[f] = ((h[f * N2 + pt] + h[(5 + f) * N2 + pt]) + h[(10 + f) * N2 + pt]) + h[(15 + f) * N2 + pt];
       } else {
         const double* qn = Qin + sSrc[task];
         const double* own = sQ + fel * N3;
@@ -459,3 +460,4 @@ int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMe
   hipLaunchKernelGGL(k_varp_mortar, dim3(grid), dim3(64 * kMortarWaves), 0, stream, tb, m, Qin);
   return (int)hipGetLastError();
 }
+

@@ -1,6 +1,7 @@
 // Host side of the variable-degree entry points (dg_varp_* in dg.h): the
-// per-degree element lists, node offsets, mortar tables, workspace carve-up
-// and the per-degree launch sequence.
+// elements of the (optionally refined) mesh, their node offsets, face table
+// and per-(degree, size) element lists, the mortar tables, workspace
+// carve-up and the launch sequence.
 
 #include <hip/hip_runtime.h>
 
@@ -27,15 +28,16 @@ double lagrange_at(const double* xi, int n, int t, double x) {
 
 struct Timed {
   hipEvent_t a, b;
-  int slot;   // 3 p + mode, or kMortarSlot
+  int slot;   // 3 p + mode, kMortarSlot or kHangSlot
 };
 
 constexpr int kMortarSlot = 3 * DG_VARP_MAXN;
+constexpr int kHangSlot = kMortarSlot + 1;
 // pencil of the element lists' visiting order (elements along x, planes
 // along z), as the single-degree kernel's default
 constexpr int kPencilX = 16;
 constexpr int kPencilZ = 8;
-constexpr int kSlots = kMortarSlot + 1;
+constexpr int kSlots = kHangSlot + 1;
 
 }  // namespace
 
@@ -46,14 +48,17 @@ struct dg_varp {
   double L[3] = {1.0, 1.0, 1.0};
   int maxn = 0;
   std::vector<int> deg;          // per element
+  std::vector<int> level;        // per element: 0 a whole cell, 1 a child of a refined cell
   std::vector<int64_t> off;      // E + 1
-  std::vector<int> list;         // grouped by degree
-  std::vector<int64_t> slot;     // [E][6] mortar flux place, -1 where conforming
+  std::vector<int> list;         // grouped by (degree, level)
+  std::vector<int64_t> face;     // [E][6] (place << 2) | DG_FACE_*
   std::vector<DGVarpFace> faces; // mortar faces grouped by degree pair
+  std::vector<DGVarpHang> hangs; // hanging sub-faces grouped by (nc, nf)
   int64_t fbuf_doubles = 0;
-  int first[DG_VARP_MAXN + 1] = {0};   // list range of point count N
-  int count[DG_VARP_MAXN + 1] = {0};
-  DGTables tab[DG_VARP_MAXN + 1];
+  // list range of point count N and level
+  int first[DG_VARP_MAXN + 1][2] = {};
+  int count[DG_VARP_MAXN + 1][2] = {};
+  DGTables tab[DG_VARP_MAXN + 1][2];
   DGVarpTabs* htabs = nullptr;   // host copy
   hipStream_t stream = nullptr;
   char* ws = nullptr;
@@ -74,17 +79,18 @@ struct dg_varp {
 namespace {
 
 struct Layout {
-  size_t off_tabs, off_off, off_slot, off_list, off_faces, off_fbuf, off_q2, total;
+  size_t off_tabs, off_off, off_face, off_list, off_faces, off_hangs, off_fbuf, off_q2, total;
 };
 
 Layout layout(const dg_varp* v) {
   Layout L;
   L.off_tabs = 0;
   L.off_off = al256(sizeof(DGVarpTabs));
-  L.off_slot = L.off_off + al256(sizeof(int64_t) * (v->E + 1));
-  L.off_list = L.off_slot + al256(sizeof(int64_t) * 6 * v->E);
+  L.off_face = L.off_off + al256(sizeof(int64_t) * (v->E + 1));
+  L.off_list = L.off_face + al256(sizeof(int64_t) * 6 * v->E);
   L.off_faces = L.off_list + al256(sizeof(int) * v->E);
-  L.off_fbuf = L.off_faces + al256(sizeof(DGVarpFace) * v->faces.size());
+  L.off_hangs = L.off_faces + al256(sizeof(DGVarpFace) * v->faces.size());
+  L.off_fbuf = L.off_hangs + al256(sizeof(DGVarpHang) * v->hangs.size());
   L.off_q2 = L.off_fbuf + al256(sizeof(double) * v->fbuf_doubles);
   L.total = L.off_q2 + al256((size_t)5 * v->T * sizeof(double));
   return L;
@@ -106,15 +112,14 @@ DGVarpMesh mesh_of(const dg_varp* v) {
   DGVarpMesh m;
   m.tabs = (const DGVarpTabs*)(v->ws + L.off_tabs);
   m.off = (const int64_t*)(v->ws + L.off_off);
-  m.slot = (const int64_t*)(v->ws + L.off_slot);
+  m.face = (const int64_t*)(v->ws + L.off_face);
   m.list = (const int*)(v->ws + L.off_list);
   m.faces = (const DGVarpFace*)(v->ws + L.off_faces);
+  m.hangs = (const DGVarpHang*)(v->ws + L.off_hangs);
   m.fbuf = (double*)(v->ws + L.off_fbuf);
   m.T = v->T;
-  m.nx = v->nx;
-  m.ny = v->ny;
-  m.nz = v->nz;
   m.nfaces = (int)v->faces.size();
+  m.nhangs = (int)v->hangs.size();
   return m;
 }
 
@@ -145,50 +150,70 @@ Timed* timer(dg_varp* v, int slot, int* err) {
   return tm;
 }
 
-// The mortar launch, then one launch per degree present.
+// The mortar and hanging-face launches, then one launch per (degree, level)
+// present.
 int launch_all(dg_varp* v, const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt) {
   const DGVarpMesh m = mesh_of(v);
   int err = 0;
   if (m.nfaces > 0) {
     Timed* tm = timer(v, kMortarSlot, &err);
     if (err) return err;
-    err = dg_launch_varp_mortar(v->stream, v->tab[1], m, Qin);
+    err = dg_launch_varp_mortar(v->stream, v->tab[1][0], m, Qin);
+    if (err) return err;
+    if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
+  }
+  if (m.nhangs > 0) {
+    Timed* tm = timer(v, kHangSlot, &err);
+    if (err) return err;
+    err = dg_launch_varp_hanging(v->stream, v->tab[1][0], m, Qin);
     if (err) return err;
     if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
   }
   for (int N = v->maxn; N >= 1; --N) {
-    if (!v->count[N]) continue;
-    Timed* tm = timer(v, 3 * (N - 1) + mode, &err);
-    if (err) return err;
-    err = dg_launch_varp(v->stream, N, v->tab[N], m, v->first[N], v->count[N], Qin, Qout, RR, mode, a, b, dt);
-    if (err) return err;
-    if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
+    for (int lev = 0; lev < 2; ++lev) {
+      if (!v->count[N][lev]) continue;
+      Timed* tm = timer(v, 3 * (N - 1) + mode, &err);
+      if (err) return err;
+      err = dg_launch_varp(v->stream, N, v->tab[N][lev], m, v->first[N][lev], v->count[N][lev], Qin, Qout, RR, mode,
+                           a, b, dt);
+      if (err) return err;
+      if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
+    }
   }
   return 0;
 }
 
-}  // namespace
+dg_varp* fail_null(int code, const char* what) {
+  dg_set_error(code, "%s", what);
+  return nullptr;
+}
 
-extern "C" {
-
-dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double* L, double gamma) {
+// The elements of the mesh (cell by cell; a refined cell's eight children in
+// the order (kz, ky, kx), kx fastest), their offsets, face table, mortar and
+// hanging faces, element lists and tables.  refine: NULL for no refinement.
+dg_varp* build(int nx, int ny, int nz, const int* refine, const int* degrees, const double* L, double gamma) {
   if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz > 0x7fffffffLL) {
     dg_set_error(DG_EINVAL, "bad mesh size %d x %d x %d", nx, ny, nz);
     return nullptr;
   }
-  if (!degrees || !L) {
-    dg_set_error(DG_EINVAL, "NULL degrees or L");
-    return nullptr;
+  if (!degrees || !L) return fail_null(DG_EINVAL, "NULL degrees or L");
+  if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail_null(DG_EINVAL, "gamma must be finite and > 1");
+  if (!(L[0] > 0) || !(L[1] > 0) || !(L[2] > 0) || !std::isfinite(L[0] + L[1] + L[2]))
+    return fail_null(DG_EINVAL, "domain lengths must be finite and > 0");
+  const int64_t C = (int64_t)nx * ny * nz;
+  int64_t E = 0;
+  bool any_refined = false;
+  for (int64_t c = 0; c < C; ++c) {
+    const int r = refine ? refine[c] : 0;
+    if (r != 0 && r != 1) {
+      dg_set_error(DG_EINVAL, "cell %lld: refinement %d is not 0 or 1", (long long)c, r);
+      return nullptr;
+    }
+    any_refined = any_refined || r;
+    E += r ? 8 : 1;
   }
-  if (!(gamma > 1.0) || !std::isfinite(gamma)) {
-    dg_set_error(DG_EINVAL, "gamma must be finite and > 1");
-    return nullptr;
-  }
-  if (!(L[0] > 0) || !(L[1] > 0) || !(L[2] > 0) || !std::isfinite(L[0] + L[1] + L[2])) {
-    dg_set_error(DG_EINVAL, "domain lengths must be finite and > 0");
-    return nullptr;
-  }
-  const int64_t E = (int64_t)nx * ny * nz;
+  if (E > 0x7fffffffLL || (any_refined && 8 * C > 0x7fffffffLL))
+    return fail_null(DG_EUNSUPPORTED, "more than 2^31-1 elements");
   for (int64_t e = 0; e < E; ++e) {
     if (degrees[e] < 0 || degrees[e] >= DG_VARP_MAXN) {
       dg_set_error(DG_EUNSUPPORTED, "element %lld: degree %d outside 0..%d", (long long)e, degrees[e],
@@ -197,15 +222,11 @@ dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double
     }
   }
   dg_varp* v = new (std::nothrow) dg_varp;
-  if (!v) {
-    dg_set_error(DG_EINVAL, "out of host memory");
-    return nullptr;
-  }
+  if (!v) return fail_null(DG_EINVAL, "out of host memory");
   v->htabs = new (std::nothrow) DGVarpTabs;
   if (!v->htabs) {
     delete v;
-    dg_set_error(DG_EINVAL, "out of host memory");
-    return nullptr;
+    return fail_null(DG_EINVAL, "out of host memory");
   }
   v->nx = nx;
   v->ny = ny;
@@ -214,6 +235,18 @@ dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double
   v->gamma = gamma;
   for (int d = 0; d < 3; ++d) v->L[d] = L[d];
   v->deg.assign(degrees, degrees + E);
+  // elements cell by cell; cfirst[c]: the first element of cell c
+  std::vector<int64_t> cfirst(C + 1);
+  v->level.resize(E);
+  {
+    int64_t e = 0;
+    for (int64_t c = 0; c < C; ++c) {
+      cfirst[c] = e;
+      const int n = (refine && refine[c]) ? 8 : 1;
+      for (int k = 0; k < n; ++k) v->level[e++] = n == 8;
+    }
+    cfirst[C] = e;
+  }
   v->off.resize(E + 1);
   int64_t T = 0;
   for (int64_t e = 0; e < E; ++e) {
@@ -224,89 +257,188 @@ dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double
   }
   v->off[E] = T;
   v->T = T;
-  // element lists by degree, each in the single-degree kernel's visiting
-  // order: z-slabs of kPencilZ planes, inside a slab pencils of kPencilX
-  // elements along x, inside a pencil y-row by y-row, then z, x fastest (an
-  // element's y- and z-neighbours of the same degree are listed close to
-  // it, so their reads meet in L2)
-  std::vector<int> cnt(DG_VARP_MAXN + 1, 0);
-  for (int64_t e = 0; e < E; ++e) ++cnt[v->deg[e] + 1];
+  // element lists by (degree, level), each in the single-degree kernel's
+  // visiting order over the cells: z-slabs of kPencilZ planes, inside a slab
+  // pencils of kPencilX cells along x, inside a pencil y-row by y-row, then
+  // z, x fastest; a refined cell's children together (an element's y- and
+  // z-neighbours of the same group are listed close to it, so their reads
+  // meet in L2)
+  std::vector<int> cnt((DG_VARP_MAXN + 1) * 2, 0);
+  for (int64_t e = 0; e < E; ++e) ++cnt[(v->deg[e] + 1) * 2 + v->level[e]];
   int pos = 0;
   for (int N = DG_VARP_MAXN; N >= 1; --N) {
-    v->first[N] = pos;
-    v->count[N] = cnt[N];
-    pos += cnt[N];
+    for (int lev = 0; lev < 2; ++lev) {
+      v->first[N][lev] = pos;
+      v->count[N][lev] = cnt[N * 2 + lev];
+      pos += cnt[N * 2 + lev];
+    }
   }
   v->list.resize(E);
-  std::vector<int> fill(v->first, v->first + DG_VARP_MAXN + 1);
   {
+    std::vector<int> fill((DG_VARP_MAXN + 1) * 2, 0);
+    for (int N = 1; N <= DG_VARP_MAXN; ++N)
+      for (int lev = 0; lev < 2; ++lev) fill[N * 2 + lev] = v->first[N][lev];
     const int px = std::min(kPencilX, nx), pz = std::min(kPencilZ, nz);
     for (int zs = 0; zs < nz; zs += pz)
       for (int xs = 0; xs < nx; xs += px)
         for (int y = 0; y < ny; ++y)
           for (int z = zs; z < std::min(zs + pz, nz); ++z)
             for (int x = xs; x < std::min(xs + px, nx); ++x) {
-              const int64_t e = ((int64_t)z * ny + y) * nx + x;
-              v->list[fill[v->deg[e] + 1]++] = (int)e;
+              const int64_t c = ((int64_t)z * ny + y) * nx + x;
+              for (int64_t e = cfirst[c]; e < cfirst[c + 1]; ++e)
+                v->list[fill[(v->deg[e] + 1) * 2 + v->level[e]]++] = (int)e;
             }
   }
-  // per-degree tables (the single-degree library's), Gauss-Legendre rules
+  // per-(degree, level) tables (the single-degree library's on the mesh of
+  // that element size), Gauss-Legendre rules
   double xi[DG_VARP_MAXN + 1][DG_MAXN], w[DG_VARP_MAXN + 1][DG_MAXN];
   DGVarpTabs& H = *v->htabs;
   std::memset(&H, 0, sizeof(H));
   for (int N = 1; N <= DG_VARP_MAXN; ++N) {
-    dg_build_tables(nx, ny, nz, N - 1, gamma, v->L, &v->tab[N], xi[N], w[N]);
+    dg_build_tables(nx, ny, nz, N - 1, gamma, v->L, &v->tab[N][0], xi[N], w[N]);
+    if (any_refined)
+      dg_build_tables(2 * nx, 2 * ny, 2 * nz, N - 1, gamma, v->L, &v->tab[N][1], xi[N], w[N]);
+    else
+      v->tab[N][1] = v->tab[N][0];
     for (int m = 0; m < N; ++m) {
-      H.lm[N][m] = v->tab[N].lm[m];
-      H.lp[N][m] = v->tab[N].lp[m];
+      H.lm[N][m] = v->tab[N][0].lm[m];
+      H.lp[N][m] = v->tab[N][0].lp[m];
     }
   }
   for (int n = 1; n <= DG_VARP_MAXN; ++n) {
-    for (int M = n + 1; M <= DG_VARP_MAXN; ++M) {
+    for (int M = n; M <= DG_VARP_MAXN; ++M) {
       for (int b = 0; b < M; ++b) {
         for (int t = 0; t < n; ++t) {
-          const double l = lagrange_at(xi[n], n, t, xi[M][b]);
-          H.interp[n][M][b * n + t] = l;
-          H.proj[n][M][t * M + b] = l * w[M][b] / w[n][t];
+          if (M > n) {
+            const double l = lagrange_at(xi[n], n, t, xi[M][b]);
+            H.interp[n][M][b * n + t] = l;
+            H.proj[n][M][t * M + b] = l * w[M][b] / w[n][t];
+          }
+          for (int h = 0; h < 2; ++h) {
+            const double l = lagrange_at(xi[n], n, t, 0.5 * (xi[M][b] + 2 * h - 1));
+            H.hinterp[n][M][h][b * n + t] = l;
+            H.hproj[n][M][h][t * M + b] = 0.5 * l * w[M][b] / w[n][t];
+          }
         }
       }
     }
   }
-  // mortar faces: every +d face whose neighbour has another degree; each
-  // side's projected flux gets its own place in the face-flux buffer
-  v->slot.assign(6 * E, -1);
-  for (int64_t e = 0; e < E; ++e) {
-    const int ex = (int)(e % nx), ey = (int)((e / nx) % ny), ez = (int)(e / ((int64_t)nx * ny));
+  // faces: every element's +d face once, as the oracle's enumeration: a
+  // sibling or a same-size neighbour (conforming, or a mortar face between
+  // degrees), or hanging sub-faces (fine against coarse: one; coarse
+  // against a refined cell: four)
+  v->face.assign(6 * E, -1);
+  auto el_of = [&](int64_t c, int kx, int ky, int kz) { return cfirst[c] + (kz * 2 + ky) * 2 + kx; };
+  auto same_size = [&](int64_t a, int64_t b, int d) {
+    const int na = v->deg[a] + 1, nb = v->deg[b] + 1;
+    if (na == nb) {
+      v->face[6 * a + 2 * d + 1] = (v->off[b] << 2) | DG_FACE_CONFORMING;
+      v->face[6 * b + 2 * d] = (v->off[a] << 2) | DG_FACE_CONFORMING;
+      return;
+    }
+    DGVarpFace F;
+    F.oa = v->off[a];
+    F.ob = v->off[b];
+    F.d = d;
+    const int lo = std::min(na, nb), hi = std::max(na, nb);
+    F.code = (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (na < nb ? 1 : 0);
+    F.sa = v->fbuf_doubles;
+    v->fbuf_doubles += 5 * (int64_t)na * na;
+    F.sb = v->fbuf_doubles;
+    v->fbuf_doubles += 5 * (int64_t)nb * nb;
+    v->face[6 * a + 2 * d + 1] = (F.sa << 2) | DG_FACE_MORTAR;
+    v->face[6 * b + 2 * d] = (F.sb << 2) | DG_FACE_MORTAR;
+    v->faces.push_back(F);
+  };
+  // sub-face of coarse element ec (its face 2d + cside) against fine ef on
+  // quarter (q1, q2)
+  auto hanging = [&](int64_t ec, int64_t ef, int d, int cside, int q1, int q2) {
+    const int nc = v->deg[ec] + 1, nf = v->deg[ef] + 1;
+    int64_t& cf = v->face[6 * ec + 2 * d + cside];
+    if (cf < 0) {
+      cf = (v->fbuf_doubles << 2) | DG_FACE_HANGING;
+      v->fbuf_doubles += 20 * (int64_t)nc * nc;
+    }
+    DGVarpHang G;
+    G.oc = v->off[ec];
+    G.of = v->off[ef];
+    G.sc = (cf >> 2) + (int64_t)(2 * q2 + q1) * 5 * nc * nc;
+    G.sf = v->fbuf_doubles;
+    v->fbuf_doubles += 5 * (int64_t)nf * nf;
+    G.d = d;
+    G.nc = nc;
+    G.nf = nf;
+    G.q1 = q1;
+    G.q2 = q2;
+    G.cminus = cside;
+    v->face[6 * ef + 2 * d + (1 - cside)] = (G.sf << 2) | DG_FACE_MORTAR;
+    v->hangs.push_back(G);
+  };
+  for (int64_t c = 0; c < C; ++c) {
+    const int cx = (int)(c % nx), cy = (int)((c / nx) % ny), cz = (int)(c / ((int64_t)nx * ny));
+    const bool rc = refine && refine[c];
     for (int d = 0; d < 3; ++d) {
-      const int x = d == 0 ? (ex + 1) % nx : ex, y = d == 1 ? (ey + 1) % ny : ey, z = d == 2 ? (ez + 1) % nz : ez;
-      const int64_t nb = ((int64_t)z * ny + y) * nx + x;
-      const int na = v->deg[e] + 1, nn = v->deg[nb] + 1;
-      if (na == nn) continue;
-      DGVarpFace F;
-      F.oa = v->off[e];
-      F.ob = v->off[nb];
-      F.d = d;
-      const int lo = std::min(na, nn), hi = std::max(na, nn);
-      F.code = (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (na < nn ? 1 : 0);
-      F.sa = v->fbuf_doubles;
-      v->fbuf_doubles += 5 * (int64_t)na * na;
-      F.sb = v->fbuf_doubles;
-      v->fbuf_doubles += 5 * (int64_t)nn * nn;
-      v->slot[6 * e + 2 * d + 1] = F.sa;
-      v->slot[6 * nb + 2 * d] = F.sb;
-      v->faces.push_back(F);
+      const int x = d == 0 ? (cx + 1) % nx : cx, y = d == 1 ? (cy + 1) % ny : cy, z = d == 2 ? (cz + 1) % nz : cz;
+      const int64_t cn = ((int64_t)z * ny + y) * nx + x;
+      const bool rn = refine && refine[cn];
+      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;   // tangential axes, ascending
+      if (!rc && !rn) {
+        same_size(cfirst[c], cfirst[cn], d);
+        continue;
+      }
+      for (int kz = 0; kz < 2; ++kz)
+        for (int ky = 0; ky < 2; ++ky)
+          for (int kx = 0; kx < 2; ++kx) {
+            int k[3] = {kx, ky, kz};
+            if (rc) {
+              const int64_t e = el_of(c, kx, ky, kz);
+              if (k[d] == 0) {   // the sibling across the cell's midplane
+                k[d] = 1;
+                same_size(e, el_of(c, k[0], k[1], k[2]), d);
+              } else if (rn) {   // the neighbour cell's child across the cell face
+                k[d] = 0;
+                same_size(e, el_of(cn, k[0], k[1], k[2]), d);
+              } else {           // fine e (-d side) against the coarse neighbour
+                hanging(cfirst[cn], e, d, 0, k[t0], k[t1]);
+              }
+            } else if (k[d] == 0) {   // coarse c (-d side) against the refined neighbour's children
+              hanging(cfirst[c], el_of(cn, kx, ky, kz), d, 1, k[t0], k[t1]);
+            }
+          }
     }
   }
-  if (v->faces.size() > 0x7fffffffu) {
-    delete v;
-    dg_set_error(DG_EUNSUPPORTED, "more than 2^31-1 faces between degrees");
-    return nullptr;
+  for (int64_t i = 0; i < 6 * E; ++i) {
+    if (v->face[i] < 0) {
+      delete v;
+      return fail_null(DG_EINVAL, "internal error: an element face without a neighbour");
+    }
   }
-  // waves that run together mostly take the same degree pair
+  if (v->faces.size() > 0x7fffffffu || v->hangs.size() > 0x7fffffffu) {
+    delete v;
+    return fail_null(DG_EUNSUPPORTED, "more than 2^31-1 faces between degrees or sizes");
+  }
+  // waves that run together mostly take the same kernel branch
   std::stable_sort(v->faces.begin(), v->faces.end(),
-                   [](const DGVarpFace& x, const DGVarpFace& y) { return (x.code >> 1) < (y.code >> 1); });
+                   [](const DGVarpFace& a, const DGVarpFace& b) { return (a.code >> 1) < (b.code >> 1); });
+  std::stable_sort(v->hangs.begin(), v->hangs.end(), [](const DGVarpHang& a, const DGVarpHang& b) {
+    return a.nc * (DG_VARP_MAXN + 1) + a.nf < b.nc * (DG_VARP_MAXN + 1) + b.nf;
+  });
   dg_set_error(DG_OK, "");
   return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_varp* dg_varp_create(int nx, int ny, int nz, const int* degrees, const double* L, double gamma) {
+  return build(nx, ny, nz, nullptr, degrees, L, gamma);
+}
+
+dg_varp* dg_varp_create_refined(int nx, int ny, int nz, const int* refine, const int* degrees, const double* L,
+                                double gamma) {
+  if (!refine) return fail_null(DG_EINVAL, "NULL refine");
+  return build(nx, ny, nz, refine, degrees, L, gamma);
 }
 
 void dg_varp_destroy(dg_varp* v) { delete v; }
@@ -318,6 +450,8 @@ int dg_varp_set_stream(dg_varp* v, void* s) {
 }
 
 int64_t dg_varp_num_dof(const dg_varp* v) { return v ? v->T : -1; }
+
+int64_t dg_varp_num_elements(const dg_varp* v) { return v ? v->E : -1; }
 
 int64_t dg_varp_offset(const dg_varp* v, int64_t e) {
   if (!v || e < 0 || e > v->E) return -1;
@@ -337,12 +471,17 @@ int dg_varp_set_workspace(dg_varp* v, void* dptr, size_t bytes) {
   v->uploaded = false;
   int err = (int)hipMemcpy(v->ws + L.off_tabs, v->htabs, sizeof(DGVarpTabs), hipMemcpyHostToDevice);
   if (err) return hipfail(err, "upload mortar tables");
-  err = (int)hipMemcpy(v->ws + L.off_slot, v->slot.data(), sizeof(int64_t) * 6 * v->E, hipMemcpyHostToDevice);
-  if (err) return hipfail(err, "upload face slots");
+  err = (int)hipMemcpy(v->ws + L.off_face, v->face.data(), sizeof(int64_t) * 6 * v->E, hipMemcpyHostToDevice);
+  if (err) return hipfail(err, "upload face table");
   if (!v->faces.empty()) {
     err = (int)hipMemcpy(v->ws + L.off_faces, v->faces.data(), sizeof(DGVarpFace) * v->faces.size(),
                          hipMemcpyHostToDevice);
     if (err) return hipfail(err, "upload mortar faces");
+  }
+  if (!v->hangs.empty()) {
+    err = (int)hipMemcpy(v->ws + L.off_hangs, v->hangs.data(), sizeof(DGVarpHang) * v->hangs.size(),
+                         hipMemcpyHostToDevice);
+    if (err) return hipfail(err, "upload hanging faces");
   }
   err = (int)hipMemcpy(v->ws + L.off_off, v->off.data(), sizeof(int64_t) * (v->E + 1), hipMemcpyHostToDevice);
   if (err) return hipfail(err, "upload offsets");

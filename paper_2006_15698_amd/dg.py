@@ -104,6 +104,9 @@ _SIGS = {
     "dg_batch_rk_steps": (_i, [_vp, _vp, _vp, _i]),
     "dg_batch_graph_steps": (_i, [_vp, _vp, _vp, _i]),
     "dg_varp_create": (_vp, [_i, _i, _i, ctypes.POINTER(ctypes.c_int), _dp, _d]),
+    "dg_varp_create_refined": (_vp, [_i, _i, _i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp,
+                                     _d]),
+    "dg_varp_num_elements": (_i64, [_vp]),
     "dg_varp_destroy": (None, [_vp]),
     "dg_varp_set_stream": (_i, [_vp, _vp]),
     "dg_varp_num_dof": (_i64, [_vp]),
@@ -502,8 +505,32 @@ def dg_varp_create(nx, ny, nz, degrees, L=(1.0, 1.0, 1.0), gamma=1.4):
     return v
 
 
+def dg_varp_create_refined(nx, ny, nz, refine, degrees, L=(1.0, 1.0, 1.0), gamma=1.4):
+    """refine: nx ny nz values 0/1 in cell order c = (cz ny + cy) nx + cx;
+    degrees: one per element, cell by cell, a refined cell's eight children
+    in the order (kz, ky, kx)."""
+    ref = [int(v) for v in np.asarray(refine).reshape(-1)]
+    if len(ref) != nx * ny * nz:
+        raise ValueError(f"{len(ref)} refinement flags for {nx * ny * nz} cells")
+    deg = [int(v) for v in np.asarray(degrees).reshape(-1)]
+    E = nx * ny * nz + 7 * sum(1 for r in ref if r)
+    if len(deg) != E:
+        raise ValueError(f"{len(deg)} degrees for {E} elements")
+    ra = (ctypes.c_int * len(ref))(*ref)
+    da = (ctypes.c_int * len(deg))(*deg)
+    La = (ctypes.c_double * 3)(*[float(v) for v in L])
+    v = _lib.dg_varp_create_refined(int(nx), int(ny), int(nz), ra, da, La, float(gamma))
+    if not v:
+        raise DGError(DG_EINVAL, dg_last_error())
+    return v
+
+
 def dg_varp_destroy(v):
     _lib.dg_varp_destroy(v)
+
+
+def dg_varp_num_elements(v):
+    return int(_lib.dg_varp_num_elements(v))
 
 
 def dg_varp_set_stream(v, stream=None):
@@ -540,34 +567,50 @@ def dg_varp_set_timing(v, on):
     return _check(_lib.dg_varp_set_timing(v, int(on)))
 
 
+DG_VARP_TIMING_SLOTS = 26
+
+
 def dg_varp_timing_read(v):
     """{(p, mode): (ms, launches)} for the launches recorded since timing
-    was switched on (mode 0 rhs, 1 stages 2..5, 2 first stage), and
-    "mortar": (ms, launches) for the kernel of the faces between degrees."""
-    ms = (ctypes.c_double * 25)()
-    cnt = (ctypes.c_int64 * 25)()
+    was switched on (mode 0 rhs, 1 stages 2..5, 2 first stage; both element
+    sizes), "mortar": (ms, launches) for the kernel of the faces between
+    degrees and "hanging" for the hanging-face kernel."""
+    ms = (ctypes.c_double * DG_VARP_TIMING_SLOTS)()
+    cnt = (ctypes.c_int64 * DG_VARP_TIMING_SLOTS)()
     _check(_lib.dg_varp_timing_read(v, ms, cnt))
     out = {(i // 3, i % 3): (ms[i], cnt[i]) for i in range(24) if cnt[i]}
     if cnt[24]:
         out["mortar"] = (ms[24], cnt[24])
+    if cnt[25]:
+        out["hanging"] = (ms[25], cnt[25])
     return out
 
 
 class VariableDegree:
-    """Periodic nx*ny*nz mesh with a degree per element (degrees[ez, ey, ex],
-    0..7).  State: a flat float64 tensor of 5 T values, field f at
-    [f T, (f + 1) T), element e's nodes at offsets[e] .. offsets[e + 1]."""
+    """Periodic mesh of nx*ny*nz cells with a degree per element.  Without
+    refine: one element per cell, degrees[ez, ey, ex] (0..7).  With refine
+    (refine[cz, cy, cx] in {0, 1}): a refined cell is eight elements of half
+    its size, elements cell by cell with a refined cell's children in the
+    order (kz, ky, kx), and degrees one per element in that order.  State: a
+    flat float64 tensor of 5 T values, field f at [f T, (f + 1) T), element
+    e's nodes at offsets[e] .. offsets[e + 1]."""
 
-    def __init__(self, n, degrees, L=(1.0, 1.0, 1.0), gamma=1.4, device=None):
+    def __init__(self, n, degrees, L=(1.0, 1.0, 1.0), gamma=1.4, device=None, refine=None):
         self.nx, self.ny, self.nz = (int(v) for v in n)
-        self.deg = np.asarray(degrees, dtype=np.int64).reshape(self.nz, self.ny, self.nx)
         self.L = tuple(float(v) for v in L)
         self.gamma = float(gamma)
         self.device = torch.device(device or "cuda")
-        self.v = dg_varp_create(self.nx, self.ny, self.nz, self.deg, self.L, self.gamma)
+        if refine is None:
+            self.refine = None
+            self.deg = np.asarray(degrees, dtype=np.int64).reshape(self.nz, self.ny, self.nx)
+            self.v = dg_varp_create(self.nx, self.ny, self.nz, self.deg, self.L, self.gamma)
+        else:
+            self.refine = np.asarray(refine, dtype=np.int64).reshape(self.nz, self.ny, self.nx)
+            self.deg = np.asarray(degrees, dtype=np.int64).reshape(-1)
+            self.v = dg_varp_create_refined(self.nx, self.ny, self.nz, self.refine, self.deg, self.L, self.gamma)
         self.T = dg_varp_num_dof(self.v)
-        E = self.nx * self.ny * self.nz
-        self.offsets = [dg_varp_offset(self.v, e) for e in range(E + 1)]
+        self.E = dg_varp_num_elements(self.v)
+        self.offsets = [dg_varp_offset(self.v, e) for e in range(self.E + 1)]
         nbytes = dg_varp_workspace_bytes(self.v)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         aligned = (self.workspace.data_ptr() + 255) & ~255

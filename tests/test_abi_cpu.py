@@ -182,6 +182,28 @@ def test_paired_line_lane_map(tmp_path):
     assert "ok" in out.stdout
 
 
+def test_varp_mesh_tables(dg, tmp_path):
+    """The variable-degree builder's tables, checked on the host by a
+    program compiled with the builder's own source: geometric neighbours of
+    every face, the quarter of every hanging face, every face-flux double
+    written once and every element face reading only written doubles, the
+    element lists a partition by (degree, size) -- 241 seeded meshes."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "varp_mesh_check")
+    libdir = os.path.dirname(dg.LIB_PATH)
+    cmd = [hipcc, "-O1", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_2006_15698_amd", "csrc"), os.path.join(ROOT, "tests", "varp_mesh_check.cpp"),
+           "-o", exe, "-L", libdir, "-ldg", f"-Wl,-rpath,{libdir}"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "ok" in out.stdout
+
+
 def test_varp_host_logic(dg):
     """Variable-degree context: degree checks, node offsets (element blocks
     back to back), and workspace checks, all before any device access."""
@@ -213,3 +235,33 @@ def test_varp_host_logic(dg):
         assert lib.dg_varp_rk_steps(v, Q, R, ctypes.c_double(1e-3), 1) == dg.DG_EWORKSPACE
     finally:
         dg.dg_varp_destroy(v)
+
+
+def test_refined_host_logic(dg):
+    """Refined-mesh context: refinement and degree checks, element count
+    (a refined cell is eight elements), node offsets in element order, the
+    workspace growing with the hanging faces' flux blocks."""
+    lib = dg._lib
+    with pytest.raises(dg.DGError, match="refinement 2"):
+        dg.dg_varp_create_refined(2, 1, 1, [2, 0], [1] * 9)
+    with pytest.raises(dg.DGError, match="degree 8"):
+        dg.dg_varp_create_refined(2, 1, 1, [1, 0], [1] * 8 + [8])
+    with pytest.raises(ValueError, match="degrees for 9 elements"):
+        dg.dg_varp_create_refined(2, 1, 1, [1, 0], [1, 1])
+    assert lib.dg_varp_create_refined(2, 1, 1, None, (ctypes.c_int * 2)(1, 1), (ctypes.c_double * 3)(1, 1, 1),
+                                      ctypes.c_double(1.4)) is None
+    ref = np.array([1, 0, 0, 1, 0, 0])   # 3 x 2 x 1 cells
+    deg = np.arange(2 * 8 + 4) % 6
+    v = dg.dg_varp_create_refined(3, 2, 1, ref, deg)
+    u = dg.dg_varp_create(3, 2, 1, [1] * 6)
+    try:
+        assert dg.dg_varp_num_elements(v) == 20 and dg.dg_varp_num_elements(u) == 6
+        off = np.concatenate([[0], np.cumsum((deg + 1) ** 3)])
+        assert dg.dg_varp_num_dof(v) == off[-1]
+        assert [dg.dg_varp_offset(v, e) for e in range(21)] == list(off)
+        nb = dg.dg_varp_workspace_bytes(v)
+        assert nb >= 5 * off[-1] * 8 * 2 and nb % 256 == 0
+        assert lib.dg_varp_rhs(v, 0x10000000, 0x20000000) == dg.DG_EWORKSPACE
+    finally:
+        dg.dg_varp_destroy(v)
+        dg.dg_varp_destroy(u)
