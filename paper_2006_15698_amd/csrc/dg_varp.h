@@ -24,8 +24,8 @@ struct DGVarpTabs {
   // surface integral on the mortar, lifted by the diagonal mass matrix)
   double proj[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][DG_VARP_MAXN * DG_VARP_MAXN];
   // the same on one half of a coarse face (h = 0: xi in [-1, 0], h = 1:
-  // [0, 1]), at xi = (x^m_b + 2h - 1) / 2, for any m; the projection
-  // carries the half's factor 1/2 (a sub-face is a quarter of the coarse
+  // [0, 1]), at xi = (x^m_b + 2h - 1) / 2, for m >= n; the projection
+  // carries the half's factor 1/2 (a fine face is a quarter of the coarse
   // face: 1/2 per direction)
   double hinterp[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][2][DG_VARP_MAXN * DG_VARP_MAXN];
   double hproj[DG_VARP_MAXN + 1][DG_VARP_MAXN + 1][2][DG_VARP_MAXN * DG_VARP_MAXN];
@@ -41,24 +41,25 @@ struct DGVarpFace {
   int code;            // (lo * (DG_VARP_MAXN + 1) + hi) * 2 + (1 if a has the lower degree)
 };
 
-// A hanging sub-face: a quarter (q1, q2 along the two tangential axes in
-// increasing order) of a coarse element's face against a whole face of a
-// fine element.  oc, of: first nodes; sc: the coarse side's block for this
-// quarter ([5][N_c^2]), sf: the fine side's ([5][N_f^2]); cminus: the
-// coarse element is on the -d side (its +d face).
+// A coarse face against the four fine faces of a refined neighbour cell
+// (hanging faces): quarter q = 2 q2 + q1 (q1, q2 the halves along the two
+// tangential axes in increasing order) is the whole face of fine element
+// q.  oc, of[q]: first nodes; sc: the coarse side's summed projection
+// ([5][N_c^2]); sf[q]: fine element q's ([5][N_f^2]); cminus: the coarse
+// element is on the -d side (its +d face).
 struct DGVarpHang {
-  int64_t oc, of, sc, sf;
-  int d, nc, nf, q1, q2, cminus;
+  int64_t oc, sc;
+  int64_t of[4], sf[4];
+  int nf[4];
+  int d, nc, cminus, pad;
 };
 
 // What a face of an element takes its flux from: the low two bits of
 // DGVarpMesh::face, the rest (face >> 2) the place it names.
 enum {
   DG_FACE_CONFORMING = 0,  // same size and degree: the neighbour's first node
-  DG_FACE_MORTAR = 1,      // the projected flux [5][N^2] in fbuf (a face between
-                           // degrees, or a fine element's face on a coarse one)
-  DG_FACE_HANGING = 2      // a coarse face on four fine ones: the first of the
-                           // quarters' blocks [4][5][N^2] in fbuf (q = 2 q2 + q1)
+  DG_FACE_MORTAR = 1       // the projected flux [5][N^2] in fbuf (a face between
+                           // degrees, or either side of a hanging face)
 };
 
 // Mesh description read by every launch.
@@ -68,7 +69,7 @@ struct DGVarpMesh {
   const int* list;         // elements grouped by (degree, size), each group in visiting order
   const DGVarpTabs* tabs;
   const DGVarpFace* faces; // the mortar faces, grouped by code
-  const DGVarpHang* hangs; // the hanging sub-faces, grouped by (nc, nf)
+  const DGVarpHang* hangs; // the coarse faces with hanging faces, grouped by degree
   double* fbuf;            // projected fluxes of the mortar and hanging faces
   int64_t T;               // total nodes
   int nfaces, nhangs;
@@ -80,12 +81,17 @@ struct DGVarpMesh {
 // Reads the mortar and hanging fluxes written for the same Qin.
 int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMesh& m, int first, int count,
                    const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt);
-// The flux of every mortar face of Qin, projected onto both sides' face
-// nodes, into m.fbuf.
-int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin);
-// The flux of every hanging sub-face of Qin, projected onto the fine
-// side's face nodes and the coarse side's quarter block, into m.fbuf.
-int dg_launch_varp_hanging(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin);
+// The flux of the mortar faces [begin, begin + count) of Qin, all between
+// degrees lo - 1 < hi - 1 (point counts lo, hi), projected onto both sides'
+// face nodes, into m.fbuf.
+int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int lo,
+                          int hi, int begin, int count);
+// The flux of every hanging face of Qin, projected onto the fine sides'
+// face nodes and (summed over the four quarters) the coarse side's, into
+// m.fbuf.
+// (The coarse faces [begin, begin + count), all of nc points.)
+int dg_launch_varp_hanging(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int nc,
+                           int begin, int count);
 // Elements per workgroup of the variable-degree kernel for N points.
 int dg_varp_epb(int N);
 

@@ -17,15 +17,17 @@
 // xi_b the mortar points in the element's own coordinate: x^M_b on a face
 // of the mortar's size (F* itself where the element's face nodes are the
 // mortar points), (x^M_b + 2h - 1) / 2 on half h of a coarse face; a coarse
-// face against four fine ones sums the four quarters' projections.
+// face against four fine ones takes the sum of the four quarters'
+// projections.
 //
-// k_varp_mortar: one wave per face between degrees (same size; faces grouped
-//   by degree pair): the lower-degree side's trace at its face nodes into
+// k_varp_mortar<NLO, NHI>: one launch per degree pair, one wave per face
+//   between those degrees (same size): the lower-degree side's trace at its face nodes into
 //   LDS, the higher side's trace at its face nodes (the mortar points) in
 //   registers, the lower side's trace interpolated to the mortar points, the
 //   flux, written for the higher side and projected for the lower side into
 //   the face-flux buffer.
-// k_varp_hanging (kern_varp_hang.hip): one wave per hanging sub-face.
+// k_varp_hanging (kern_varp_hang.hip): one workgroup per coarse face with
+//   hanging faces, one wave per quarter.
 // k_varp<N, MODE>: a workgroup owns EPB elements of one degree and size from
 // that group's element list (in pencil order; each XCD takes a contiguous
 // part), one thread per node:
@@ -35,8 +37,7 @@
 //      conforming face the neighbour's trace interpolated from its state
 //      along the normal line (global memory), the own trace from LDS and the
 //      flux (the chains of the single-degree kernel); otherwise the
-//      projected flux from the buffer (the sum of the four quarters, in a
-//      fixed order, on a coarse face against fine ones);
+//      projected flux from the buffer;
 //   C/D. the volume contraction, lift and RK update of the single-degree
 //      neighbour-read kernel, in the same order, so that a mesh of one degree
 //      and size gives bitwise the results of that kernel.
@@ -194,28 +195,29 @@ __device__ __forceinline__ void mortar_face(const DGTables& tb, const DGVarpTabs
 
 constexpr int kMortarWaves = 4;
 
+// One launch per degree pair present (the faces sorted by pair, faces
+// [begin, begin + count) of the pair), so that each pair's kernel has its
+// own register count: 82-128 VGPRs for the pairs up to (5, 6) against 138
+// for one kernel holding every pair.
+template <int NLO, int NHI>
 __global__ void __launch_bounds__(64 * kMortarWaves) k_varp_mortar(const DGTables tb, const DGVarpMesh m,
-                                                                    const double* __restrict__ Qin) {
+                                                                    const double* __restrict__ Qin, int begin,
+                                                                    int count) {
   __shared__ double sg[kMortarWaves][640];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int fi = blockIdx.x * kMortarWaves + wave;
-  if (fi >= m.nfaces) return;   // whole waves: no workgroup barrier below
-  const DGVarpFace F = m.faces[fi];
-  const DGVarpTabs* __restrict__ tabs = m.tabs;
-  double* g = sg[wave];
-#define VARP_PAIR(LO, HI) \
-  case (LO) * (DG_VARP_MAXN + 1) + (HI): mortar_face<LO, HI>(tb, tabs, m, F, Qin, g, lane); break;
-  switch (F.code >> 1) {   // uniform over the wave
-    VARP_PAIR(1, 2) VARP_PAIR(1, 3) VARP_PAIR(1, 4) VARP_PAIR(1, 5) VARP_PAIR(1, 6) VARP_PAIR(1, 7) VARP_PAIR(1, 8)
-    VARP_PAIR(2, 3) VARP_PAIR(2, 4) VARP_PAIR(2, 5) VARP_PAIR(2, 6) VARP_PAIR(2, 7) VARP_PAIR(2, 8)
-    VARP_PAIR(3, 4) VARP_PAIR(3, 5) VARP_PAIR(3, 6) VARP_PAIR(3, 7) VARP_PAIR(3, 8)
-    VARP_PAIR(4, 5) VARP_PAIR(4, 6) VARP_PAIR(4, 7) VARP_PAIR(4, 8)
-    VARP_PAIR(5, 6) VARP_PAIR(5, 7) VARP_PAIR(5, 8)
-    VARP_PAIR(6, 7) VARP_PAIR(6, 8)
-    VARP_PAIR(7, 8)
-    default: break;
-  }
-#undef VARP_PAIR
+  if (fi >= count) return;   // whole waves: no workgroup barrier below
+  const DGVarpFace F = m.faces[begin + fi];
+  mortar_face<NLO, NHI>(tb, m.tabs, m, F, Qin, sg[wave], lane);
+}
+
+template <int NLO, int NHI>
+int launch_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int begin,
+                  int count) {
+  const unsigned grid = (unsigned)((count + kMortarWaves - 1) / kMortarWaves);
+  hipLaunchKernelGGL((k_varp_mortar<NLO, NHI>), dim3(grid), dim3(64 * kMortarWaves), 0, stream, tb, m, Qin, begin,
+                     count);
+  return (int)hipGetLastError();
 }
 
 template <int N, int MODE>
@@ -307,17 +309,10 @@ __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_e
     if (i < FP && fel < ne) {
       const int task = face * EPB + fel;
       double fs[5];
-      const int kind = sKind[task];
-      if (kind == DG_FACE_MORTAR) {
+      if (sKind[task] == DG_FACE_MORTAR) {
         const double* h = mesh.fbuf + sSrc[task];
 #pragma unroll
         for (int f = 0; f < 5; ++f) fs[f] = h[f * N2 + pt];
-      } else if (kind == DG_FACE_HANGING) {
-        // the four quarters' projections, in the order q = 0..3
-        const double* h = mesh.fbuf + sSrc[task];
-#pragma unroll
-        for (int f = 0; f < 5; ++f)
-          fs[f] = ((h[f * N2 + pt] + h[(5 + f) * N2 + pt]) + h[(10 + f) * N2 + pt]) + h[(15 + f) * N2 + pt];
       } else {
         const double* qn = Qin + sSrc[task];
         const double* own = sQ + fel * N3;
@@ -453,11 +448,21 @@ int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMe
 #undef CALL
 }
 
-int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin) {
+int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int lo,
+                          int hi, int begin, int count) {
   using namespace dgdev;
-  if (m.nfaces <= 0) return 0;
-  const unsigned grid = (unsigned)((m.nfaces + kMortarWaves - 1) / kMortarWaves);
-  hipLaunchKernelGGL(k_varp_mortar, dim3(grid), dim3(64 * kMortarWaves), 0, stream, tb, m, Qin);
-  return (int)hipGetLastError();
+  if (count <= 0) return 0;
+#define VARP_PAIR(LO, HI) \
+  case (LO) * (DG_VARP_MAXN + 1) + (HI): return launch_mortar<LO, HI>(stream, tb, m, Qin, begin, count);
+  switch (lo * (DG_VARP_MAXN + 1) + hi) {
+    VARP_PAIR(1, 2) VARP_PAIR(1, 3) VARP_PAIR(1, 4) VARP_PAIR(1, 5) VARP_PAIR(1, 6) VARP_PAIR(1, 7) VARP_PAIR(1, 8)
+    VARP_PAIR(2, 3) VARP_PAIR(2, 4) VARP_PAIR(2, 5) VARP_PAIR(2, 6) VARP_PAIR(2, 7) VARP_PAIR(2, 8)
+    VARP_PAIR(3, 4) VARP_PAIR(3, 5) VARP_PAIR(3, 6) VARP_PAIR(3, 7) VARP_PAIR(3, 8)
+    VARP_PAIR(4, 5) VARP_PAIR(4, 6) VARP_PAIR(4, 7) VARP_PAIR(4, 8)
+    VARP_PAIR(5, 6) VARP_PAIR(5, 7) VARP_PAIR(5, 8)
+    VARP_PAIR(6, 7) VARP_PAIR(6, 8)
+    VARP_PAIR(7, 8)
+    default: return (int)hipErrorInvalidValue;
+  }
+#undef VARP_PAIR
 }
-

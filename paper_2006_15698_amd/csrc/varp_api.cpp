@@ -53,8 +53,14 @@ struct dg_varp {
   std::vector<int> list;         // grouped by (degree, level)
   std::vector<int64_t> face;     // [E][6] (place << 2) | DG_FACE_*
   std::vector<DGVarpFace> faces; // mortar faces grouped by degree pair
-  std::vector<DGVarpHang> hangs; // hanging sub-faces grouped by (nc, nf)
+  std::vector<DGVarpHang> hangs; // coarse faces with hanging faces, grouped by degree
   int64_t fbuf_doubles = 0;
+  // ranges of the sorted mortar faces per degree pair (index lo * 9 + hi)
+  // and of the sorted coarse faces per coarse point count
+  int pair_first[(DG_VARP_MAXN + 1) * (DG_VARP_MAXN + 1)] = {};
+  int pair_count[(DG_VARP_MAXN + 1) * (DG_VARP_MAXN + 1)] = {};
+  int hang_first[DG_VARP_MAXN + 1] = {};
+  int hang_count[DG_VARP_MAXN + 1] = {};
   // list range of point count N and level
   int first[DG_VARP_MAXN + 1][2] = {};
   int count[DG_VARP_MAXN + 1][2] = {};
@@ -150,23 +156,31 @@ Timed* timer(dg_varp* v, int slot, int* err) {
   return tm;
 }
 
-// The mortar and hanging-face launches, then one launch per (degree, level)
-// present.
+// The mortar launches (one per degree pair present) and hanging-face
+// launches (one per coarse degree present), each group timed as one, then
+// one launch per (degree, level) present.
 int launch_all(dg_varp* v, const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt) {
   const DGVarpMesh m = mesh_of(v);
   int err = 0;
   if (m.nfaces > 0) {
     Timed* tm = timer(v, kMortarSlot, &err);
     if (err) return err;
-    err = dg_launch_varp_mortar(v->stream, v->tab[1][0], m, Qin);
-    if (err) return err;
+    for (int code = 0; code < (DG_VARP_MAXN + 1) * (DG_VARP_MAXN + 1); ++code) {
+      if (!v->pair_count[code]) continue;
+      err = dg_launch_varp_mortar(v->stream, v->tab[1][0], m, Qin, code / (DG_VARP_MAXN + 1),
+                                  code % (DG_VARP_MAXN + 1), v->pair_first[code], v->pair_count[code]);
+      if (err) return err;
+    }
     if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
   }
   if (m.nhangs > 0) {
     Timed* tm = timer(v, kHangSlot, &err);
     if (err) return err;
-    err = dg_launch_varp_hanging(v->stream, v->tab[1][0], m, Qin);
-    if (err) return err;
+    for (int nc = 1; nc <= DG_VARP_MAXN; ++nc) {
+      if (!v->hang_count[nc]) continue;
+      err = dg_launch_varp_hanging(v->stream, v->tab[1][0], m, Qin, nc, v->hang_first[nc], v->hang_count[nc]);
+      if (err) return err;
+    }
     if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
   }
   for (int N = v->maxn; N >= 1; --N) {
@@ -350,29 +364,33 @@ dg_varp* build(int nx, int ny, int nz, const int* refine, const int* degrees, co
     v->face[6 * b + 2 * d] = (F.sb << 2) | DG_FACE_MORTAR;
     v->faces.push_back(F);
   };
-  // sub-face of coarse element ec (its face 2d + cside) against fine ef on
-  // quarter (q1, q2)
+  // quarter (q1, q2) of coarse element ec's face 2d + cside against fine
+  // element ef: the coarse face's record (its summed projection block) on
+  // first use, the fine side's block per quarter
+  std::vector<int64_t> hang_of(any_refined ? 6 * E : 0, -1);
   auto hanging = [&](int64_t ec, int64_t ef, int d, int cside, int q1, int q2) {
     const int nc = v->deg[ec] + 1, nf = v->deg[ef] + 1;
-    int64_t& cf = v->face[6 * ec + 2 * d + cside];
-    if (cf < 0) {
-      cf = (v->fbuf_doubles << 2) | DG_FACE_HANGING;
-      v->fbuf_doubles += 20 * (int64_t)nc * nc;
+    int64_t& hi = hang_of[6 * ec + 2 * d + cside];
+    if (hi < 0) {
+      DGVarpHang G{};
+      G.oc = v->off[ec];
+      G.sc = v->fbuf_doubles;
+      v->fbuf_doubles += 5 * (int64_t)nc * nc;
+      G.d = d;
+      G.nc = nc;
+      G.cminus = cside;
+      for (int q = 0; q < 4; ++q) G.nf[q] = 0;
+      v->face[6 * ec + 2 * d + cside] = (G.sc << 2) | DG_FACE_MORTAR;
+      hi = (int64_t)v->hangs.size();
+      v->hangs.push_back(G);
     }
-    DGVarpHang G;
-    G.oc = v->off[ec];
-    G.of = v->off[ef];
-    G.sc = (cf >> 2) + (int64_t)(2 * q2 + q1) * 5 * nc * nc;
-    G.sf = v->fbuf_doubles;
+    DGVarpHang& G = v->hangs[hi];
+    const int q = 2 * q2 + q1;
+    G.of[q] = v->off[ef];
+    G.sf[q] = v->fbuf_doubles;
+    G.nf[q] = nf;
     v->fbuf_doubles += 5 * (int64_t)nf * nf;
-    G.d = d;
-    G.nc = nc;
-    G.nf = nf;
-    G.q1 = q1;
-    G.q2 = q2;
-    G.cminus = cside;
-    v->face[6 * ef + 2 * d + (1 - cside)] = (G.sf << 2) | DG_FACE_MORTAR;
-    v->hangs.push_back(G);
+    v->face[6 * ef + 2 * d + (1 - cside)] = (G.sf[q] << 2) | DG_FACE_MORTAR;
   };
   for (int64_t c = 0; c < C; ++c) {
     const int cx = (int)(c % nx), cy = (int)((c / nx) % ny), cz = (int)(c / ((int64_t)nx * ny));
@@ -415,14 +433,29 @@ dg_varp* build(int nx, int ny, int nz, const int* refine, const int* degrees, co
   }
   if (v->faces.size() > 0x7fffffffu || v->hangs.size() > 0x7fffffffu) {
     delete v;
-    return fail_null(DG_EUNSUPPORTED, "more than 2^31-1 faces between degrees or sizes");
+    return fail_null(DG_EUNSUPPORTED, "more than 2^31-1 faces between degrees or coarse faces with hanging faces");
   }
   // waves that run together mostly take the same kernel branch
   std::stable_sort(v->faces.begin(), v->faces.end(),
                    [](const DGVarpFace& a, const DGVarpFace& b) { return (a.code >> 1) < (b.code >> 1); });
-  std::stable_sort(v->hangs.begin(), v->hangs.end(), [](const DGVarpHang& a, const DGVarpHang& b) {
-    return a.nc * (DG_VARP_MAXN + 1) + a.nf < b.nc * (DG_VARP_MAXN + 1) + b.nf;
-  });
+  for (const DGVarpHang& G : v->hangs) {
+    if (!G.nf[0] || !G.nf[1] || !G.nf[2] || !G.nf[3]) {
+      delete v;
+      return fail_null(DG_EINVAL, "internal error: a coarse face without its four quarters");
+    }
+  }
+  std::stable_sort(v->hangs.begin(), v->hangs.end(),
+                   [](const DGVarpHang& a, const DGVarpHang& b) { return a.nc < b.nc; });
+  for (size_t i = 0; i < v->faces.size(); ++i) {
+    const int code = v->faces[i].code >> 1;
+    if (!v->pair_count[code]) v->pair_first[code] = (int)i;
+    ++v->pair_count[code];
+  }
+  for (size_t i = 0; i < v->hangs.size(); ++i) {
+    const int nc = v->hangs[i].nc;
+    if (!v->hang_count[nc]) v->hang_first[nc] = (int)i;
+    ++v->hang_count[nc];
+  }
   dg_set_error(DG_OK, "");
   return v;
 }

@@ -10,11 +10,12 @@
 //     buffer;
 //   - every mortar face joins two touching elements of the same size and
 //     different degrees, with the degree pair its code names;
-//   - every hanging sub-face joins a coarse element and a fine one whose face
-//     is the quarter (q1, q2) of the coarse face, touching across it;
+//   - every coarse face with hanging faces has one record, whose quarter
+//     q = 2 q2 + q1 is the whole face of a fine element touching across it;
 //   - the kernels write every double of the face-flux buffer exactly once,
 //     and every element face reads only written doubles of its own blocks;
-//   - the element lists hold every element once, grouped by (degree, size).
+//   - the element lists hold every element once, grouped by (degree, size),
+//     and the launch ranges of the mortar and hanging faces every face once.
 // Exit status 0 and "ok" on success.
 #include "varp_api.cpp"
 
@@ -104,29 +105,34 @@ int check_mesh(int nx, int ny, int nz, const std::vector<int>& ref, std::mt19937
     write(F.sa, 5LL * na * na, "mortar a");
     write(F.sb, 5LL * nb2 * nb2, "mortar b");
   }
+  std::vector<int> coarse_seen(6 * E, 0);
   for (const DGVarpHang& H : v->hangs) {
-    const int64_t c = element_at(H.oc), f = element_at(H.of);
-    CHECK(c >= 0 && f >= 0, "hanging face names no element");
-    if (c < 0 || f < 0) continue;
-    CHECK(geo[c].s == 2 && geo[f].s == 1, "hanging face sizes %d %d", geo[c].s, geo[f].s);
-    CHECK(H.nc == deg[c] + 1 && H.nf == deg[f] + 1, "hanging face degrees");
-    CHECK(H.q1 >= 0 && H.q1 < 2 && H.q2 >= 0 && H.q2 < 2 && H.d >= 0 && H.d < 3, "hanging face indices");
+    const int64_t c = element_at(H.oc);
+    CHECK(c >= 0, "hanging face names no coarse element");
+    if (c < 0) continue;
     const int d = H.d, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-    const Geo &C = geo[c], &Fi = geo[f];
-    if (H.cminus) {
-      CHECK(wrap(C.x0[d] + 2, d) == wrap(Fi.x0[d], d), "coarse -d side does not touch");
-    } else {
-      CHECK(wrap(Fi.x0[d] + 1, d) == wrap(C.x0[d], d), "fine -d side does not touch");
-    }
-    CHECK(Fi.x0[t0] == C.x0[t0] + H.q1 && Fi.x0[t1] == C.x0[t1] + H.q2, "fine face is not quarter (%d, %d)", H.q1,
-          H.q2);
-    const int64_t cf = v->face[6 * c + 2 * d + (H.cminus ? 1 : 0)];
-    CHECK((cf & 3) == DG_FACE_HANGING, "coarse face of a hanging face is not marked hanging");
-    CHECK(H.sc == (cf >> 2) + (int64_t)(2 * H.q2 + H.q1) * 5 * H.nc * H.nc, "quarter block place");
-    const int64_t ff = v->face[6 * f + 2 * d + (H.cminus ? 0 : 1)];
-    CHECK(ff == ((H.sf << 2) | DG_FACE_MORTAR), "fine face of a hanging face does not name its block");
+    CHECK(d >= 0 && d < 3 && geo[c].s == 2 && H.nc == deg[c] + 1, "coarse side of a hanging face");
+    const int cface = 2 * d + (H.cminus ? 1 : 0);
+    CHECK(++coarse_seen[6 * c + cface] == 1, "coarse face %lld/%d has two records", (long long)c, cface);
+    CHECK(v->face[6 * c + cface] == ((H.sc << 2) | DG_FACE_MORTAR), "coarse face does not name its block");
     write(H.sc, 5LL * H.nc * H.nc, "hanging coarse");
-    write(H.sf, 5LL * H.nf * H.nf, "hanging fine");
+    const Geo& C = geo[c];
+    for (int q = 0; q < 4; ++q) {
+      const int64_t f = element_at(H.of[q]);
+      CHECK(f >= 0, "hanging face names no fine element");
+      if (f < 0) continue;
+      const Geo& Fi = geo[f];
+      CHECK(Fi.s == 1 && H.nf[q] == deg[f] + 1, "fine side of quarter %d", q);
+      if (H.cminus) {
+        CHECK(wrap(C.x0[d] + 2, d) == wrap(Fi.x0[d], d), "coarse -d side does not touch");
+      } else {
+        CHECK(wrap(Fi.x0[d] + 1, d) == wrap(C.x0[d], d), "fine -d side does not touch");
+      }
+      CHECK(Fi.x0[t0] == C.x0[t0] + (q & 1) && Fi.x0[t1] == C.x0[t1] + (q >> 1), "fine face is not quarter %d", q);
+      const int64_t ff = v->face[6 * f + 2 * d + (H.cminus ? 0 : 1)];
+      CHECK(ff == ((H.sf[q] << 2) | DG_FACE_MORTAR), "fine face of a hanging face does not name its block");
+      write(H.sf[q], 5LL * H.nf[q] * H.nf[q], "hanging fine");
+    }
   }
   for (int64_t i = 0; i < nb; ++i) CHECK(written[i] == 1, "buffer double %lld written %d times", (long long)i,
                                          written[i]);
@@ -136,7 +142,7 @@ int check_mesh(int nx, int ny, int nz, const std::vector<int>& ref, std::mt19937
       const int64_t fr = v->face[6 * e + f];
       const int kind = (int)(fr & 3), d = f >> 1, side = f & 1;
       const int64_t place = fr >> 2;
-      CHECK(fr >= 0 && kind <= DG_FACE_HANGING, "element %lld face %d unset", (long long)e, f);
+      CHECK(fr >= 0 && kind <= DG_FACE_MORTAR, "element %lld face %d unset", (long long)e, f);
       if (kind == DG_FACE_CONFORMING) {
         const int64_t b = element_at(place);
         CHECK(b >= 0, "conforming face names no element");
@@ -145,14 +151,27 @@ int check_mesh(int nx, int ny, int nz, const std::vector<int>& ref, std::mt19937
         CHECK(side ? touches_plus(e, b, d) : touches_plus(b, e, d), "conforming neighbour of %lld face %d is wrong",
               (long long)e, f);
       } else {
-        const int64_t len = (kind == DG_FACE_HANGING ? 20LL : 5LL) * N * N;
+        const int64_t len = 5LL * N * N;
         CHECK(place >= 0 && place + len <= nb, "face block outside the buffer");
         if (place < 0 || place + len > nb) continue;
         for (int64_t i = place; i < place + len; ++i) CHECK(written[i] == 1, "face reads an unwritten double");
-        CHECK(kind != DG_FACE_HANGING || geo[e].s == 2, "a fine element's face marked hanging");
       }
     }
   }
+  // the per-launch ranges: each degree pair's mortar faces and each coarse
+  // degree's coarse faces, together every face once
+  int64_t nface = 0, nhang = 0;
+  for (int code = 0; code < (DG_VARP_MAXN + 1) * (DG_VARP_MAXN + 1); ++code) {
+    for (int i = v->pair_first[code]; i < v->pair_first[code] + v->pair_count[code]; ++i)
+      CHECK(i >= 0 && i < (int)v->faces.size() && (v->faces[i].code >> 1) == code, "mortar range of pair %d", code);
+    nface += v->pair_count[code];
+  }
+  for (int nc = 0; nc <= DG_VARP_MAXN; ++nc) {
+    for (int i = v->hang_first[nc]; i < v->hang_first[nc] + v->hang_count[nc]; ++i)
+      CHECK(i >= 0 && i < (int)v->hangs.size() && v->hangs[i].nc == nc, "coarse-face range of %d points", nc);
+    nhang += v->hang_count[nc];
+  }
+  CHECK(nface == (int64_t)v->faces.size() && nhang == (int64_t)v->hangs.size(), "launch ranges miss faces");
   std::vector<int> seen(E, 0);
   for (int N = 1; N <= DG_VARP_MAXN; ++N)
     for (int lev = 0; lev < 2; ++lev)
