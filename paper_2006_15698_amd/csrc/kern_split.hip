@@ -19,8 +19,10 @@
 //   flux of the standard scheme there.  With the central two-point flux this
 //   is exactly the standard weak form.
 //
-// One workgroup per element, one thread per node (the pairwise fluxes make
-// the volume term O(N^4) per element).  The last two terms of B_f depend on
+// One workgroup per element (elements visited in the neighbour-read stage's
+// order: pencils, each XCD a contiguous part), one thread per node (the
+// pairwise fluxes make the volume term O(N^4) per element); the face points
+// of each direction on waves of their own.  The last two terms of B_f depend on
 // the face point only, not on the node along the line: they are formed once
 // per face point in the face phase, so a node evaluates N + 2 two-point
 // fluxes per direction and each face point N (3N + 6 per node and 6 per
@@ -31,6 +33,7 @@
 
 #include "dg_internal.h"
 #include "stage_fp64.h"
+#include "stage_nb.h"
 
 namespace {
 
@@ -38,9 +41,17 @@ template <int N>
 struct SCfg {
   static constexpr int N2 = N * N;
   static constexpr int N3 = N * N * N;
-  // whole waves covering the nodes and the 6 N^2 face points (the face
-  // phase in one round)
-  static constexpr int NT = (N3 > 6 * N2 ? N3 : 6 * N2) <= 64 ? 64 : ((N3 > 6 * N2 ? N3 : 6 * N2) + 63) / 64 * 64;
+  // N >= 5: the face points of one direction (both sides) on WPD waves of
+  // their own, so that the direction is uniform over a wave; below, where a
+  // direction's points fill at most half a wave, the 6 N^2 points in order
+  // (separate waves would add waves that idle in the volume phase)
+  static constexpr bool WAVES = 2 * N2 > 32;
+  static constexpr int WPD = (2 * N2 + 63) / 64;
+  // whole waves covering the nodes and the face phase in one round (a wave
+  // that took two directions one after the other would hold both variants'
+  // registers, and spilled)
+  static constexpr int NF = WAVES ? 3 * WPD * 64 : 6 * N2;
+  static constexpr int NT = ((N3 > NF ? N3 : NF) + 63) / 64 * 64;
 };
 
 // Primitive description of a state: rho, u, v, w, p, e = E / rho.
@@ -153,17 +164,70 @@ __device__ __forceinline__ void face_line_sum(const double (*P)[SCfg<N>::N3], co
   }
 }
 
+// Face point i (side s = i / N^2, point pt) of direction D: the element's own
+// trace and its neighbour's (interpolated from their states along the normal
+// line), the Lax-Friedrichs flux, and into LDS the point's G term and its
+// own trace's primitives.  The side is a per-lane select, so lanes of both
+// sides of a direction run the same instructions.
+template <int N, int D>
+__device__ __forceinline__ void split_face(const DGTables& tb, const double* __restrict__ Qin, int64_t fs, int e,
+                                           int i, const double (*P)[SCfg<N>::N3], double (*Tp)[6][SCfg<N>::N2],
+                                           double (*G)[5][SCfg<N>::N2]) {
+  constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3;
+  const int s = i / N2, pt = i - s * N2;
+  const int face = 2 * D + s;
+  const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, D, s ? 1 : -1);
+  const double* qe = Qin + (int64_t)e * N3;
+  const double* qn = Qin + (int64_t)en * N3;
+  double own[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, nbr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int node = dgdev::tnode<N>(D, m, pt);
+    const double wo = s ? tb.lp[m] : tb.lm[m];   // own trace on this face
+    const double wn = s ? tb.lm[m] : tb.lp[m];   // the neighbour's trace on its opposite face
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      own[f] = fma(wo, qe[f * fs + node], own[f]);
+      nbr[f] = fma(wn, qn[f * fs + node], nbr[f]);
+    }
+  }
+  // the face's -d side state first
+  double mn[5], pl[5], fl[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    mn[f] = s ? own[f] : nbr[f];
+    pl[f] = s ? nbr[f] : own[f];
+  }
+  dgdev::lf_flux_d<D>(mn, pl, tb.gamma, tb.gm1, fl);
+  const Prim so = to_prim(own, tb.gm1);
+  double c[N], sf[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < N; ++a) c[a] = s ? tb.lp[a] : tb.lm[a];
+  face_line_sum<N, D>(P, so, c, pt, sf);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) G[face][f][pt] = fl[f] - sf[f];
+  Tp[face][0][pt] = so.r;
+  Tp[face][1][pt] = so.u[0];
+  Tp[face][2][pt] = so.u[1];
+  Tp[face][3][pt] = so.u[2];
+  Tp[face][4][pt] = so.p;
+  Tp[face][5][pt] = so.e;
+}
+
 template <int N, int MODE>
 __global__ void __launch_bounds__(SCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR, double a,
-        double b, double dt) {
-  constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3, NT = SCfg<N>::NT;
+        double b, double dt, DGOrder ord) {
+  constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3, WPD = SCfg<N>::WPD;
   __shared__ double P[6][N3];        // node primitives
   __shared__ double Tp[6][6][N2];    // own trace primitives per face (2d + side)
   __shared__ double G[6][5][N2];     // per face point: Lax-Friedrichs flux - sum_a l_a f_S(Q~_f, Q_a)
   __shared__ double Dm[N][N];        // D_ia = l_a'(xi_i)
-  const int e = blockIdx.x;
+  // the element of this workgroup in the visiting order (pencils, XCD chunks)
+  int e, ne;
+  dgdev::block_elements<1>(tb, ord, blockIdx.x, gridDim.x, e, ne);
   const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
   const int64_t fs = (int64_t)tb.E * N3;
   const double* qe = Qin + (int64_t)e * N3;
   if (t < N2) {
@@ -184,40 +248,16 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
     P[5][t] = s.e;
   }
   __syncthreads();   // the face phase reads the node primitives
-  for (int fp = t; fp < 6 * N2; fp += NT) {
-    const int face = fp / N2, pt = fp % N2, d = face >> 1, s = face & 1;
-    const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
-    const double* qn = Qin + (int64_t)en * N3;
-    double own[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, nbr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int m = 0; m < N; ++m) {
-      const int node = dgdev::tnode<N>(d, m, pt);
-      const double wo = s ? tb.lp[m] : tb.lm[m];   // own trace on this face
-      const double wn = s ? tb.lm[m] : tb.lp[m];   // the neighbour's trace on its opposite face
-#pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        own[f] = fma(wo, qe[f * fs + node], own[f]);
-        nbr[f] = fma(wn, qn[f * fs + node], nbr[f]);
-      }
+  // face points: wave w < 3 WPD takes 64 points of direction w / WPD (or,
+  // below N = 5, thread t takes point t)
+  {
+    const int d = SCfg<N>::WAVES ? wave / WPD : t / (2 * N2);
+    const int fi = SCfg<N>::WAVES ? (wave - d * WPD) * 64 + lane : t - d * 2 * N2;
+    if (d < 3 && fi < 2 * N2) {
+      if (d == 0) split_face<N, 0>(tb, Qin, fs, e, fi, P, Tp, G);
+      else if (d == 1) split_face<N, 1>(tb, Qin, fs, e, fi, P, Tp, G);
+      else split_face<N, 2>(tb, Qin, fs, e, fi, P, Tp, G);
     }
-    double fl[5];
-    // the face's -d side state first
-    if (d == 0) s ? dgdev::lf_flux_d<0>(own, nbr, tb.gamma, tb.gm1, fl) : dgdev::lf_flux_d<0>(nbr, own, tb.gamma, tb.gm1, fl);
-    else if (d == 1) s ? dgdev::lf_flux_d<1>(own, nbr, tb.gamma, tb.gm1, fl) : dgdev::lf_flux_d<1>(nbr, own, tb.gamma, tb.gm1, fl);
-    else s ? dgdev::lf_flux_d<2>(own, nbr, tb.gamma, tb.gm1, fl) : dgdev::lf_flux_d<2>(nbr, own, tb.gamma, tb.gm1, fl);
-    const Prim so = to_prim(own, tb.gm1);
-    double sf[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const double* c = s ? tb.lp : tb.lm;
-    if (d == 0) face_line_sum<N, 0>(P, so, c, pt, sf);
-    else if (d == 1) face_line_sum<N, 1>(P, so, c, pt, sf);
-    else face_line_sum<N, 2>(P, so, c, pt, sf);
-#pragma unroll
-    for (int f = 0; f < 5; ++f) G[face][f][pt] = fl[f] - sf[f];
-    Tp[face][0][pt] = so.r;
-    Tp[face][1][pt] = so.u[0];
-    Tp[face][2][pt] = so.u[1];
-    Tp[face][3][pt] = so.u[2];
-    Tp[face][4][pt] = so.p;
-    Tp[face][5][pt] = so.e;
   }
   __syncthreads();
   if (t >= N3) return;
@@ -243,14 +283,15 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
 template <int N>
 int launch_split_n(const dg_ctx* c, const double* Qin, double* Qout, double* RR, int mode, double a, double b,
                    double dt) {
-  const unsigned grid = (unsigned)c->E;
+  unsigned grid;
+  const DGOrder ord = dg_order(c, 1, &grid);
   const dim3 blk(SCfg<N>::NT);
   if (mode == 0)
-    hipLaunchKernelGGL((k_split<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt);
+    hipLaunchKernelGGL((k_split<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, ord);
   else if (mode == 2)
-    hipLaunchKernelGGL((k_split<N, 2>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt);
+    hipLaunchKernelGGL((k_split<N, 2>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, ord);
   else
-    hipLaunchKernelGGL((k_split<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt);
+    hipLaunchKernelGGL((k_split<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Qin, Qout, RR, a, b, dt, ord);
   return (int)hipGetLastError();
 }
 

@@ -17,8 +17,9 @@
 // matrix divided out, as in the inviscid stage):
 //   (2/h_d) [ -sum_a Dh[i][a] X_a + l_i(+1)/w_i {X}_+ - l_i(-1)/w_i {X}_- ].
 //
-// Two launches per right-hand side, one workgroup per element, one thread
-// per node:
+// Two launches per right-hand side, one workgroup per element (elements
+// visited in the neighbour-read stage's order: pencils, each XCD a
+// contiguous part), one thread per node:
 //   k_visc_flux  Q -> F_v at every node (12 values: 4 per direction);
 //                the neighbours' primitive traces are interpolated from
 //                their state in the same launch;
@@ -30,6 +31,7 @@
 
 #include "dg_internal.h"
 #include "stage_fp64.h"
+#include "stage_nb.h"
 
 namespace {
 
@@ -134,11 +136,14 @@ __device__ __forceinline__ void flux_trace(const DGTables& tb, const double* __r
 
 template <int N>
 __global__ void __launch_bounds__(VCfg<N>::NT)
-k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, double mu, double kappa) {
+k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, double mu, double kappa,
+            DGOrder ord) {
   constexpr int N2 = VCfg<N>::N2, N3 = VCfg<N>::N3, NT = VCfg<N>::NT;
   __shared__ double P[4][N3];
   __shared__ double Tn[6][4][N2];   // face 2d + s: neighbour's trace (s = 0: -d face, 1: +d face)
-  const int e = blockIdx.x;
+  // the element of this workgroup in the visiting order (pencils, XCD chunks)
+  int e, ne;
+  dgdev::block_elements<1>(tb, ord, blockIdx.x, gridDim.x, e, ne);
   const int t = threadIdx.x;
   const int64_t fs = (int64_t)tb.E * N3;
   if (t < N3) {
@@ -201,11 +206,13 @@ k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, 
 template <int N, int MODE>
 __global__ void __launch_bounds__(VCfg<N>::NT)
 k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R, double* __restrict__ Q,
-             double* __restrict__ res, double a, double b, double dt) {
+             double* __restrict__ res, double a, double b, double dt, DGOrder ord) {
   constexpr int N2 = VCfg<N>::N2, N3 = VCfg<N>::N3, NT = VCfg<N>::NT;
   __shared__ double F[12][N3];
   __shared__ double Tn[6][4][N2];
-  const int e = blockIdx.x;
+  // the element of this workgroup in the visiting order (pencils, XCD chunks)
+  int e, ne;
+  dgdev::block_elements<1>(tb, ord, blockIdx.x, gridDim.x, e, ne);
   const int t = threadIdx.x;
   const int64_t fs = (int64_t)tb.E * N3;
   if (t < N3) {
@@ -258,16 +265,17 @@ k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R,
 template <int N>
 int launch_visc_n(const dg_ctx* c, const double* Q, double* Fv, double* R, double* Qu, double* res, int mode,
                   double a, double b, double dt, int first) {
-  const unsigned grid = (unsigned)c->E;
+  unsigned grid;
+  const DGOrder ord = dg_order(c, 1, &grid);
   const dim3 blk(VCfg<N>::NT);
-  hipLaunchKernelGGL(k_visc_flux<N>, dim3(grid), blk, 0, c->stream, c->tab, Q, Fv, c->mu, c->kappa);
+  hipLaunchKernelGGL(k_visc_flux<N>, dim3(grid), blk, 0, c->stream, c->tab, Q, Fv, c->mu, c->kappa, ord);
   if (mode == 0)
     hipLaunchKernelGGL((k_visc_apply<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, nullptr, nullptr, a, b,
-                       dt);
+                       dt, ord);
   else if (first)
-    hipLaunchKernelGGL((k_visc_apply<N, 2>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, Qu, res, a, b, dt);
+    hipLaunchKernelGGL((k_visc_apply<N, 2>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, Qu, res, a, b, dt, ord);
   else
-    hipLaunchKernelGGL((k_visc_apply<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, Qu, res, a, b, dt);
+    hipLaunchKernelGGL((k_visc_apply<N, 1>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, Qu, res, a, b, dt, ord);
   return (int)hipGetLastError();
 }
 
