@@ -88,28 +88,26 @@ __device__ __forceinline__ void kg_acc(const Prim& a, const Prim& b, double c, d
   for (int v = 0; v < 5; ++v) acc[v] = fma(c, f[v], acc[v]);
 }
 
-template <int N>
-__device__ __forceinline__ Prim lds_prim(const double (*P)[SCfg<N>::N3], int t) {
+// A state's primitives in LDS: six doubles at a 16-byte aligned place, read
+// and written as three 16-byte accesses.
+__device__ __forceinline__ Prim lds_prim(const double* p) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+  const double2 a = q[0], b = q[1], c = q[2];
   Prim s;
-  s.r = P[0][t];
-  s.u[0] = P[1][t];
-  s.u[1] = P[2][t];
-  s.u[2] = P[3][t];
-  s.p = P[4][t];
-  s.e = P[5][t];
+  s.r = a.x;
+  s.u[0] = a.y;
+  s.u[1] = b.x;
+  s.u[2] = b.y;
+  s.p = c.x;
+  s.e = c.y;
   return s;
 }
 
-template <int N>
-__device__ __forceinline__ Prim lds_tprim(const double (*T)[SCfg<N>::N2], int pt) {
-  Prim s;
-  s.r = T[0][pt];
-  s.u[0] = T[1][pt];
-  s.u[1] = T[2][pt];
-  s.u[2] = T[3][pt];
-  s.p = T[4][pt];
-  s.e = T[5][pt];
-  return s;
+__device__ __forceinline__ void lds_put(double* p, const Prim& s) {
+  double2* q = reinterpret_cast<double2*>(p);
+  q[0] = make_double2(s.r, s.u[0]);
+  q[1] = make_double2(s.u[1], s.u[2]);
+  q[2] = make_double2(s.p, s.e);
 }
 
 // Volume and face terms of direction D for node (m0 along the line, pt
@@ -118,16 +116,16 @@ __device__ __forceinline__ Prim lds_tprim(const double (*T)[SCfg<N>::N2], int pt
 // face term that does not depend on the node along the line:
 // F*_f - sum_a l_a(f) f_S(Q~_f, Q_a).
 template <int N, int D>
-__device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)[SCfg<N>::N3],
-                                           const double (*Dm)[N], const double (*Tp)[6][SCfg<N>::N2],
-                                           const double (*G)[5][SCfg<N>::N2], int m0, int pt, double* out) {
-  const Prim si = lds_prim<N>(P, dgdev::tnode<N>(D, m0, pt));
+__device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)[6], const double (*Dm)[N],
+                                           const double (*Tp)[SCfg<N>::N2][6], const double (*G)[SCfg<N>::N2][6],
+                                           int m0, int pt, double* out) {
+  const Prim si = lds_prim(P[dgdev::tnode<N>(D, m0, pt)]);
   double vol[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum_a 2 D_ia f_S(Q_i, Q_a)
   double em[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(-1) f_S(Q_i, Q_a)
   double ep[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(+1) f_S(Q_i, Q_a)
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    const Prim sa = lds_prim<N>(P, dgdev::tnode<N>(D, a, pt));
+    const Prim sa = lds_prim(P[dgdev::tnode<N>(D, a, pt)]);
     double f[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     kg_acc<D>(si, sa, 1.0, f);
 #pragma unroll
@@ -140,11 +138,11 @@ __device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)
   double br[2][5];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const Prim tf = lds_tprim<N>(Tp[2 * D + s], pt);
+    const Prim tf = lds_prim(Tp[2 * D + s][pt]);
     double fi[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     kg_acc<D>(si, tf, 1.0, fi);                  // f_S(Q_i, Q~_f)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) br[s][v] = fi[v] - (s ? ep[v] : em[v]) + G[2 * D + s][v][pt];
+    for (int v = 0; v < 5; ++v) br[s][v] = fi[v] - (s ? ep[v] : em[v]) + G[2 * D + s][pt][v];
   }
   const double sc = tb.sc[D];
 #pragma unroll
@@ -155,11 +153,11 @@ __device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)
 // sum_a l_a(f) f_S(Q~_f, Q_a) along the D-line through face point pt
 // (weights c = l(-1) or l(+1) of the face's side).
 template <int N, int D>
-__device__ __forceinline__ void face_line_sum(const double (*P)[SCfg<N>::N3], const Prim& tf, const double* c,
+__device__ __forceinline__ void face_line_sum(const double (*P)[6], const Prim& tf, const double* c,
                                               int pt, double* sf) {
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    const Prim sa = lds_prim<N>(P, dgdev::tnode<N>(D, a, pt));
+    const Prim sa = lds_prim(P[dgdev::tnode<N>(D, a, pt)]);
     kg_acc<D>(tf, sa, c[a], sf);
   }
 }
@@ -171,8 +169,8 @@ __device__ __forceinline__ void face_line_sum(const double (*P)[SCfg<N>::N3], co
 // sides of a direction run the same instructions.
 template <int N, int D>
 __device__ __forceinline__ void split_face(const DGTables& tb, const double* __restrict__ Qin, int64_t fs, int e,
-                                           int i, const double (*P)[SCfg<N>::N3], double (*Tp)[6][SCfg<N>::N2],
-                                           double (*G)[5][SCfg<N>::N2]) {
+                                           int i, const double (*P)[6], double (*Tp)[SCfg<N>::N2][6],
+                                           double (*G)[SCfg<N>::N2][6]) {
   constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3;
   const int s = i / N2, pt = i - s * N2;
   const int face = 2 * D + s;
@@ -205,13 +203,8 @@ __device__ __forceinline__ void split_face(const DGTables& tb, const double* __r
   for (int a = 0; a < N; ++a) c[a] = s ? tb.lp[a] : tb.lm[a];
   face_line_sum<N, D>(P, so, c, pt, sf);
 #pragma unroll
-  for (int f = 0; f < 5; ++f) G[face][f][pt] = fl[f] - sf[f];
-  Tp[face][0][pt] = so.r;
-  Tp[face][1][pt] = so.u[0];
-  Tp[face][2][pt] = so.u[1];
-  Tp[face][3][pt] = so.u[2];
-  Tp[face][4][pt] = so.p;
-  Tp[face][5][pt] = so.e;
+  for (int f = 0; f < 5; ++f) G[face][pt][f] = fl[f] - sf[f];
+  lds_put(Tp[face][pt], so);
 }
 
 template <int N, int MODE>
@@ -219,9 +212,10 @@ __global__ void __launch_bounds__(SCfg<N>::NT) __attribute__((amdgpu_waves_per_e
 k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, double* __restrict__ RR, double a,
         double b, double dt, DGOrder ord) {
   constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3, WPD = SCfg<N>::WPD;
-  __shared__ double P[6][N3];        // node primitives
-  __shared__ double Tp[6][6][N2];    // own trace primitives per face (2d + side)
-  __shared__ double G[6][5][N2];     // per face point: Lax-Friedrichs flux - sum_a l_a f_S(Q~_f, Q_a)
+  // per node / face point six doubles (16-byte aligned: three 16-byte accesses)
+  __shared__ __align__(16) double P[N3][6];        // node primitives
+  __shared__ __align__(16) double Tp[6][N2][6];    // own trace primitives per face (2d + side)
+  __shared__ __align__(16) double G[6][N2][6];     // per face point: Lax-Friedrichs flux - sum_a l_a f_S(Q~_f, Q_a)
   __shared__ double Dm[N][N];        // D_ia = l_a'(xi_i)
   // the element of this workgroup in the visiting order (pencils, XCD chunks)
   int e, ne;
@@ -240,12 +234,7 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
 #pragma unroll
     for (int f = 0; f < 5; ++f) q[f] = qe[f * fs + t];
     const Prim s = to_prim(q, tb.gm1);
-    P[0][t] = s.r;
-    P[1][t] = s.u[0];
-    P[2][t] = s.u[1];
-    P[3][t] = s.u[2];
-    P[4][t] = s.p;
-    P[5][t] = s.e;
+    lds_put(P[t], s);
   }
   __syncthreads();   // the face phase reads the node primitives
   // face points: wave w < 3 WPD takes 64 points of direction w / WPD (or,
