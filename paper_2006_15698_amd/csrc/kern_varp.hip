@@ -221,7 +221,7 @@ int launch_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, c
 }
 
 template <int N, int MODE>
-__global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(N == 4 ? 4 : 1, 8))) k_varp(const DGTables tb, const DGVarpMesh mesh, int first,
+__global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(N == 4 || N == 6 ? 4 : 1, 8))) k_varp(const DGTables tb, const DGVarpMesh mesh, int first,
                                                       int count, const double* __restrict__ Qin,
                                                       double* __restrict__ Qout, double* __restrict__ RR,
                                                       double rka, double rkb, double dt) {
