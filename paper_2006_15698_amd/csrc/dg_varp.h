@@ -71,6 +71,8 @@ struct DGVarpMesh {
   const DGVarpFace* faces; // the mortar faces, grouped by code
   const DGVarpHang* hangs; // the coarse faces with hanging faces, grouped by degree
   double* fbuf;            // projected fluxes of the mortar and hanging faces
+  double* tbuf;            // the elements' own traces on those faces, at the same
+                           // places as their fluxes in fbuf ([5][N^2] each)
   int64_t T;               // total nodes
   int nfaces, nhangs;
 };
@@ -78,20 +80,23 @@ struct DGVarpMesh {
 // Launch one stage (mode 0: RR = dQ/dt; 1: LSERK45 stage Qin -> Qout with
 // res = RR in place; 2: the first stage) over the `count` elements of N
 // points and one size listed from list[first] (tb: that size's tables).
-// Reads the mortar and hanging fluxes written for the same Qin.
+// Reads the mortar and hanging fluxes written for the same Qin.  traces
+// (modes 1, 2): also write every element's trace of Qout on its faces that
+// take their flux from fbuf into m.tbuf, for the next stage's face launches.
 int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMesh& m, int first, int count,
-                   const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt);
+                   const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt, bool traces);
 // The flux of the mortar faces [begin, begin + count) of Qin, all between
 // degrees lo - 1 < hi - 1 (point counts lo, hi), projected onto both sides'
-// face nodes, into m.fbuf.
+// face nodes, into m.fbuf.  from_traces: both sides' traces from m.tbuf
+// (written by the stage launches that produced Qin) instead of from Qin.
 int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int lo,
-                          int hi, int begin, int count);
+                          int hi, int begin, int count, bool from_traces);
 // The flux of every hanging face of Qin, projected onto the fine sides'
 // face nodes and (summed over the four quarters) the coarse side's, into
-// m.fbuf.
-// (The coarse faces [begin, begin + count), all of nc points.)
+// m.fbuf (the coarse faces [begin, begin + count), all of nc points).
+// from_traces as for the mortar launch.
 int dg_launch_varp_hanging(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int nc,
-                           int begin, int count);
+                           int begin, int count, bool from_traces);
 // Elements per workgroup of the variable-degree kernel for N points.
 int dg_varp_epb(int N);
 

@@ -61,6 +61,12 @@ struct VCfg {
   static constexpr int TASKS = 6 * EPB;          // (face, element) pairs
   static constexpr int WPF = (FP + 63) / 64;     // 64-point slots per face
   static constexpr int SMEM = 5 * NODES + 30 * FP + N * N + 2 * N;
+  // the new state of a stage that writes its traces: a region of its own
+  // (written in the output phase, one barrier before the traces), except
+  // at N = 3, where it would cost a workgroup per CU (the state's region is
+  // reused after a barrier instead)
+  static constexpr bool OWN_NEW = N != 3;
+  static constexpr int SMEM_TR = SMEM + (OWN_NEW ? 5 * NODES : 0);
   static_assert(TASKS <= 64, "the face tasks are looked up by one wave");
 };
 
@@ -83,10 +89,24 @@ __device__ __forceinline__ void conforming_flux(const DGTables& tb, const double
   lf_flux_d<D>(SIDE ? o : nb, SIDE ? nb : o, tb.gamma, tb.gm1, fs);
 }
 
+// An element's own trace on its face (D, SIDE) at point pt from its state in
+// LDS (field stride ostride), written at tr[f N^2].
+template <int N, int D, int SIDE>
+__device__ __forceinline__ void own_trace(const double* own, int ostride, int pt, const double* lmr,
+                                          const double* lpr, double* tr) {
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double v = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v = fma(SIDE ? lpr[m] : lmr[m], own[f * ostride + tnode<N>(D, m, pt)], v);
+    tr[f * N * N] = v;
+  }
+}
+
 // One mortar face on one wave, lower side NLO points, higher side NHI = M
 // points per direction.  g: this wave's LDS region [5][64] (traces) +
 // [5][64] (flux).
-template <int NLO, int NHI>
+template <int NLO, int NHI, bool FT>
 __device__ __forceinline__ void mortar_face(const DGTables& tb, const DGVarpTabs* __restrict__ tabs,
                                             const DGVarpMesh& m, const DGVarpFace& F,
                                             const double* __restrict__ Qin, double* g, int lane) {
@@ -111,36 +131,50 @@ __device__ __forceinline__ void mortar_face(const DGTables& tb, const DGVarpTabs
       r2[t] = I[b2 * NLO + t];
     }
   }
-  if (lane < L2) {
-    const double* q = Qin + (alo ? F.oa : F.ob);
-    const int a = lane % NLO, b = lane / NLO;
-    double w[5][NLO];
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-#pragma unroll
-      for (int k = 0; k < NLO; ++k) w[f][k] = q[f * T + rt_node<NLO>(d, k, a, b)];
-    }
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < NLO; ++k) v = fma(clo[k], w[f][k], v);
-      gL[f * 64 + lane] = v;
-    }
-  }
   double th[5];
-  if (lane < M2) {
-    const double* q = Qin + (alo ? F.ob : F.oa);
-    const int a = lane % M, b = lane / M;
+  if (FT) {
+    // both traces as the stage launches wrote them, at the sides' flux places
+    const double* tl = m.tbuf + (alo ? F.sa : F.sb);
+    const double* tt = m.tbuf + (alo ? F.sb : F.sa);
+    if (lane < L2) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      double w[M];
+      for (int f = 0; f < 5; ++f) gL[f * 64 + lane] = tl[f * L2 + lane];
+    }
+    if (lane < M2) {
 #pragma unroll
-      for (int k = 0; k < M; ++k) w[k] = q[f * T + rt_node<M>(d, k, a, b)];
-      double v = 0.0;
+      for (int f = 0; f < 5; ++f) th[f] = tt[f * M2 + lane];
+    }
+  } else {
+    if (lane < L2) {
+      const double* q = Qin + (alo ? F.oa : F.ob);
+      const int a = lane % NLO, b = lane / NLO;
+      double w[5][NLO];
 #pragma unroll
-      for (int k = 0; k < M; ++k) v = fma(chi[k], w[k], v);
-      th[f] = v;
+      for (int f = 0; f < 5; ++f) {
+#pragma unroll
+        for (int k = 0; k < NLO; ++k) w[f][k] = q[f * T + rt_node<NLO>(d, k, a, b)];
+      }
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < NLO; ++k) v = fma(clo[k], w[f][k], v);
+        gL[f * 64 + lane] = v;
+      }
+    }
+    if (lane < M2) {
+      const double* q = Qin + (alo ? F.ob : F.oa);
+      const int a = lane % M, b = lane / M;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        double w[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) w[k] = q[f * T + rt_node<M>(d, k, a, b)];
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) v = fma(chi[k], w[k], v);
+        th[f] = v;
+      }
     }
   }
   __syncwarp();
@@ -199,7 +233,7 @@ constexpr int kMortarWaves = 4;
 // [begin, begin + count) of the pair), so that each pair's kernel has its
 // own register count: 82-128 VGPRs for the pairs up to (5, 6) against 138
 // for one kernel holding every pair.
-template <int NLO, int NHI>
+template <int NLO, int NHI, bool FT>
 __global__ void __launch_bounds__(64 * kMortarWaves) k_varp_mortar(const DGTables tb, const DGVarpMesh m,
                                                                     const double* __restrict__ Qin, int begin,
                                                                     int count) {
@@ -208,19 +242,23 @@ __global__ void __launch_bounds__(64 * kMortarWaves) k_varp_mortar(const DGTable
   const int fi = blockIdx.x * kMortarWaves + wave;
   if (fi >= count) return;   // whole waves: no workgroup barrier below
   const DGVarpFace F = m.faces[begin + fi];
-  mortar_face<NLO, NHI>(tb, m.tabs, m, F, Qin, sg[wave], lane);
+  mortar_face<NLO, NHI, FT>(tb, m.tabs, m, F, Qin, sg[wave], lane);
 }
 
 template <int NLO, int NHI>
 int launch_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int begin,
-                  int count) {
+                  int count, bool ft) {
   const unsigned grid = (unsigned)((count + kMortarWaves - 1) / kMortarWaves);
-  hipLaunchKernelGGL((k_varp_mortar<NLO, NHI>), dim3(grid), dim3(64 * kMortarWaves), 0, stream, tb, m, Qin, begin,
-                     count);
+  if (ft)
+    hipLaunchKernelGGL((k_varp_mortar<NLO, NHI, true>), dim3(grid), dim3(64 * kMortarWaves), 0, stream, tb, m, Qin,
+                       begin, count);
+  else
+    hipLaunchKernelGGL((k_varp_mortar<NLO, NHI, false>), dim3(grid), dim3(64 * kMortarWaves), 0, stream, tb, m, Qin,
+                       begin, count);
   return (int)hipGetLastError();
 }
 
-template <int N, int MODE>
+template <int N, int MODE, bool TR>
 __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(N == 4 || N == 6 ? 4 : 1, 8))) k_varp(const DGTables tb, const DGVarpMesh mesh, int first,
                                                       int count, const double* __restrict__ Qin,
                                                       double* __restrict__ Qout, double* __restrict__ RR,
@@ -228,9 +266,10 @@ __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_e
   using C = VCfg<N>;
   constexpr int N2 = N * N, N3 = N2 * N, EPB = C::EPB, NODES = C::NODES, FP = C::FP;
   constexpr int TASKS = C::TASKS, WPF = C::WPF, NW = C::NW;
-  __shared__ double smem[C::SMEM];
+  __shared__ double smem[TR ? C::SMEM_TR : C::SMEM];
   __shared__ long long sSrc[TASKS];   // the place the face table names
   __shared__ int sKind[TASKS];        // DG_FACE_*
+  __shared__ int sAny;                // a task of this block takes its flux from fbuf
   double* sQ = smem;               // [5][NODES] own states; reused as sF in C
   double* sF = smem;
   double* sH = sQ + 5 * NODES;     // [6][5][FP] face flux at the own face nodes
@@ -269,6 +308,10 @@ __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_e
     }
     sSrc[lane] = src;
     sKind[lane] = kind;
+    if (TR) {
+      const unsigned long long any = __ballot(kind == DG_FACE_MORTAR);
+      if (lane == 0) sAny = any != 0ull;
+    }
   }
   if (act) {
 #pragma unroll
@@ -394,21 +437,57 @@ __global__ void __launch_bounds__(VCfg<N>::NT) __attribute__((amdgpu_waves_per_e
         RR[f * T + gofs] = r[f];
       }
     }
+    // ---- E: the new state's traces on the faces that take their flux from
+    //      fbuf, for the next stage's face launches (the same chain as the
+    //      face kernels' traces from the state, so the same values)
+    if (TR && sAny) {
+      double* sN = C::OWN_NEW ? smem + C::SMEM : sQ;
+      if (!C::OWN_NEW) __syncthreads();   // the volume phase has read sF
+      if (nthr) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) sN[f * NODES + tid] = q[f];
+      }
+      __syncthreads();
+      for (int s = wave; s < 6 * WPF; s += NW) {
+        const int face = s / WPF;
+        const int i = (s - face * WPF) * 64 + lane;
+        const int fel = i / N2, pt = i - fel * N2;
+        if (i < FP && fel < ne && sKind[face * EPB + fel] == DG_FACE_MORTAR) {
+          double* tr = mesh.tbuf + sSrc[face * EPB + fel] + pt;
+          const double* own = sN + fel * N3;
+          switch (face) {   // uniform over the wave
+            case 0: own_trace<N, 0, 0>(own, NODES, pt, lmr, lpr, tr); break;
+            case 1: own_trace<N, 0, 1>(own, NODES, pt, lmr, lpr, tr); break;
+            case 2: own_trace<N, 1, 0>(own, NODES, pt, lmr, lpr, tr); break;
+            case 3: own_trace<N, 1, 1>(own, NODES, pt, lmr, lpr, tr); break;
+            case 4: own_trace<N, 2, 0>(own, NODES, pt, lmr, lpr, tr); break;
+            default: own_trace<N, 2, 1>(own, NODES, pt, lmr, lpr, tr); break;
+          }
+        }
+      }
+    }
   }
 }
 
 template <int N>
 int launch_varp_n(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, int first, int count,
-                  const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt) {
+                  const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt, bool tr) {
   if (count <= 0) return 0;
   const unsigned grid = (unsigned)((count + VCfg<N>::EPB - 1) / VCfg<N>::EPB);
   const dim3 blk(VCfg<N>::NT);
+#define VARP_LAUNCH(MODE, TR) \
+  hipLaunchKernelGGL((k_varp<N, MODE, TR>), dim3(grid), blk, 0, stream, tb, m, first, count, Qin, Qout, RR, a, b, dt)
   if (mode == 0)
-    hipLaunchKernelGGL((k_varp<N, 0>), dim3(grid), blk, 0, stream, tb, m, first, count, Qin, Qout, RR, a, b, dt);
+    VARP_LAUNCH(0, false);
+  else if (mode == 1 && tr)
+    VARP_LAUNCH(1, true);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_varp<N, 1>), dim3(grid), blk, 0, stream, tb, m, first, count, Qin, Qout, RR, a, b, dt);
+    VARP_LAUNCH(1, false);
+  else if (tr)
+    VARP_LAUNCH(2, true);
   else
-    hipLaunchKernelGGL((k_varp<N, 2>), dim3(grid), blk, 0, stream, tb, m, first, count, Qin, Qout, RR, a, b, dt);
+    VARP_LAUNCH(2, false);
+#undef VARP_LAUNCH
   return (int)hipGetLastError();
 }
 
@@ -431,9 +510,9 @@ int dg_varp_epb(int N) {
 }
 
 int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMesh& m, int first, int count,
-                   const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt) {
+                   const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt, bool traces) {
   using namespace dgdev;
-#define CALL(n) launch_varp_n<n>(stream, tb, m, first, count, Qin, Qout, RR, mode, a, b, dt)
+#define CALL(n) launch_varp_n<n>(stream, tb, m, first, count, Qin, Qout, RR, mode, a, b, dt, traces && mode != 0)
   switch (N) {
     case 1: return CALL(1);
     case 2: return CALL(2);
@@ -449,11 +528,11 @@ int dg_launch_varp(hipStream_t stream, int N, const DGTables& tb, const DGVarpMe
 }
 
 int dg_launch_varp_mortar(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int lo,
-                          int hi, int begin, int count) {
+                          int hi, int begin, int count, bool from_traces) {
   using namespace dgdev;
   if (count <= 0) return 0;
 #define VARP_PAIR(LO, HI) \
-  case (LO) * (DG_VARP_MAXN + 1) + (HI): return launch_mortar<LO, HI>(stream, tb, m, Qin, begin, count);
+  case (LO) * (DG_VARP_MAXN + 1) + (HI): return launch_mortar<LO, HI>(stream, tb, m, Qin, begin, count, from_traces);
   switch (lo * (DG_VARP_MAXN + 1) + hi) {
     VARP_PAIR(1, 2) VARP_PAIR(1, 3) VARP_PAIR(1, 4) VARP_PAIR(1, 5) VARP_PAIR(1, 6) VARP_PAIR(1, 7) VARP_PAIR(1, 8)
     VARP_PAIR(2, 3) VARP_PAIR(2, 4) VARP_PAIR(2, 5) VARP_PAIR(2, 6) VARP_PAIR(2, 7) VARP_PAIR(2, 8)

@@ -17,7 +17,8 @@
 // waves per coarse face:
 //   1. the coarse trace at its face nodes into LDS, the five fields split
 //      over the four waves (the coarse element is read once for its four
-//      quarters);
+//      quarters; from the second RK stage of a call on, the traces come
+//      from the trace buffer that the stage launches wrote);
 //   2. wave q takes quarter q: the fine trace at its face nodes (into LDS
 //      only where the fine degree is below the mortar's), both traces
 //      interpolated to the mortar points, the flux, the fine side's
@@ -43,7 +44,7 @@ struct HangLds {
 
 // Quarter (q1, q2) of a coarse face of NC points on one wave, against a fine
 // face of NF points; the mortar rule M = max(NC, NF) points on the fine face.
-template <int NC, int NF>
+template <int NC, int NF, bool FT>
 __device__ __forceinline__ void hang_quarter(const DGTables& tb, const DGVarpTabs* __restrict__ tabs,
                                              const DGVarpMesh& m, const DGVarpHang* __restrict__ H, int q,
                                              const double* __restrict__ Qin, HangLds& s, int lane) {
@@ -69,7 +70,17 @@ __device__ __forceinline__ void hang_quarter(const DGTables& tb, const DGVarpTab
     }
   }
   double th[5];
-  if (lane < F2) {
+  if (FT) {
+    // the fine trace as its stage launch wrote it
+    if (lane < F2) {
+      const double* tf = m.tbuf + sf;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        th[f] = tf[f * F2 + lane];
+        if (NF < M) gI[f * 64 + lane] = th[f];
+      }
+    }
+  } else if (lane < F2) {
     const double* qf = Qin + H->of[q];
     const int a = lane % NF, b = lane / NF;
 #pragma unroll
@@ -180,14 +191,19 @@ __device__ __forceinline__ void hang_quarter(const DGTables& tb, const DGVarpTab
 }
 
 // One coarse face of NC points and its four quarters on the workgroup.
-template <int NC>
+template <int NC, bool FT>
 __device__ __forceinline__ void hang_coarse(const DGTables& tb, const DGVarpTabs* __restrict__ tabs,
                                             const DGVarpMesh& m, const DGVarpHang* __restrict__ H,
                                             const double* __restrict__ Qin, HangLds& s, int wave, int lane) {
   constexpr int C2 = NC * NC;
   const int d = H->d;
   // 1. the coarse trace: field f on wave f % 4
-  if (lane < C2) {
+  if (FT) {
+    // as the coarse element's stage launch wrote it
+    if (lane < C2) {
+      for (int f = wave; f < 5; f += kQuarters) s.gC[f * 64 + lane] = m.tbuf[H->sc + f * C2 + lane];
+    }
+  } else if (lane < C2) {
     const double* cc = H->cminus ? tabs->lp[NC] : tabs->lm[NC];
     const double* qc = Qin + H->oc;
     const int a = lane % NC, b = lane / NC;
@@ -204,7 +220,7 @@ __device__ __forceinline__ void hang_coarse(const DGTables& tb, const DGVarpTabs
   __syncthreads();
   // 2. quarter q = wave
 #define VARP_HANG(NF) \
-  case NF: hang_quarter<NC, NF>(tb, tabs, m, H, wave, Qin, s, lane); break;
+  case NF: hang_quarter<NC, NF, FT>(tb, tabs, m, H, wave, Qin, s, lane); break;
   switch (H->nf[wave]) {   // uniform over the wave
     VARP_HANG(1) VARP_HANG(2) VARP_HANG(3) VARP_HANG(4) VARP_HANG(5) VARP_HANG(6) VARP_HANG(7) VARP_HANG(8)
     default: break;
@@ -224,27 +240,31 @@ __device__ __forceinline__ void hang_coarse(const DGTables& tb, const DGVarpTabs
 // One launch per coarse degree present (coarse faces [begin, begin + grid)
 // of that degree), so that each has its own register count (114-126 VGPRs
 // up to NC = 6, against 144 for one kernel holding every degree).
-template <int NC>
+template <int NC, bool FT>
 __global__ void __launch_bounds__(64 * kQuarters) k_varp_hanging(const DGTables tb, const DGVarpMesh m,
                                                                   const double* __restrict__ Qin, int begin) {
   __shared__ HangLds s;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // one workgroup per coarse face: the grid has exactly the group's count
   const DGVarpHang* __restrict__ H = m.hangs + begin + blockIdx.x;
-  hang_coarse<NC>(tb, m.tabs, m, H, Qin, s, wave, lane);
+  hang_coarse<NC, FT>(tb, m.tabs, m, H, Qin, s, wave, lane);
 }
 
 }  // namespace
 }  // namespace dgdev
 
 int dg_launch_varp_hanging(hipStream_t stream, const DGTables& tb, const DGVarpMesh& m, const double* Qin, int nc,
-                           int begin, int count) {
+                           int begin, int count, bool from_traces) {
   using namespace dgdev;
   if (count <= 0) return 0;
-#define VARP_COARSE(NC)                                                                                   \
-  case NC:                                                                                                \
-    hipLaunchKernelGGL(k_varp_hanging<NC>, dim3((unsigned)count), dim3(64 * kQuarters), 0, stream, tb, m, \
-                       Qin, begin);                                                                       \
+#define VARP_COARSE(NC)                                                                                       \
+  case NC:                                                                                                    \
+    if (from_traces)                                                                                          \
+      hipLaunchKernelGGL((k_varp_hanging<NC, true>), dim3((unsigned)count), dim3(64 * kQuarters), 0, stream, tb, \
+                         m, Qin, begin);                                                                      \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_varp_hanging<NC, false>), dim3((unsigned)count), dim3(64 * kQuarters), 0, stream,    \
+                         tb, m, Qin, begin);                                                                  \
     break;
   switch (nc) {
     VARP_COARSE(1) VARP_COARSE(2) VARP_COARSE(3) VARP_COARSE(4) VARP_COARSE(5) VARP_COARSE(6) VARP_COARSE(7)

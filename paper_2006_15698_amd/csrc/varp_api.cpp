@@ -85,7 +85,7 @@ struct dg_varp {
 namespace {
 
 struct Layout {
-  size_t off_tabs, off_off, off_face, off_list, off_faces, off_hangs, off_fbuf, off_q2, total;
+  size_t off_tabs, off_off, off_face, off_list, off_faces, off_hangs, off_fbuf, off_tbuf, off_q2, total;
 };
 
 Layout layout(const dg_varp* v) {
@@ -97,7 +97,8 @@ Layout layout(const dg_varp* v) {
   L.off_faces = L.off_list + al256(sizeof(int) * v->E);
   L.off_hangs = L.off_faces + al256(sizeof(DGVarpFace) * v->faces.size());
   L.off_fbuf = L.off_hangs + al256(sizeof(DGVarpHang) * v->hangs.size());
-  L.off_q2 = L.off_fbuf + al256(sizeof(double) * v->fbuf_doubles);
+  L.off_tbuf = L.off_fbuf + al256(sizeof(double) * v->fbuf_doubles);
+  L.off_q2 = L.off_tbuf + al256(sizeof(double) * v->fbuf_doubles);
   L.total = L.off_q2 + al256((size_t)5 * v->T * sizeof(double));
   return L;
 }
@@ -123,6 +124,7 @@ DGVarpMesh mesh_of(const dg_varp* v) {
   m.faces = (const DGVarpFace*)(v->ws + L.off_faces);
   m.hangs = (const DGVarpHang*)(v->ws + L.off_hangs);
   m.fbuf = (double*)(v->ws + L.off_fbuf);
+  m.tbuf = (double*)(v->ws + L.off_tbuf);
   m.T = v->T;
   m.nfaces = (int)v->faces.size();
   m.nhangs = (int)v->hangs.size();
@@ -158,8 +160,11 @@ Timed* timer(dg_varp* v, int slot, int* err) {
 
 // The mortar launches (one per degree pair present) and hanging-face
 // launches (one per coarse degree present), each group timed as one, then
-// one launch per (degree, level) present.
-int launch_all(dg_varp* v, const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt) {
+// one launch per (degree, level) present.  from_traces: the face launches
+// read the traces that the stage launches producing Qin wrote; traces: the
+// stage launches write those of Qout.
+int launch_all(dg_varp* v, const double* Qin, double* Qout, double* RR, int mode, double a, double b, double dt,
+               bool from_traces, bool traces) {
   const DGVarpMesh m = mesh_of(v);
   int err = 0;
   if (m.nfaces > 0) {
@@ -168,7 +173,7 @@ int launch_all(dg_varp* v, const double* Qin, double* Qout, double* RR, int mode
     for (int code = 0; code < (DG_VARP_MAXN + 1) * (DG_VARP_MAXN + 1); ++code) {
       if (!v->pair_count[code]) continue;
       err = dg_launch_varp_mortar(v->stream, v->tab[1][0], m, Qin, code / (DG_VARP_MAXN + 1),
-                                  code % (DG_VARP_MAXN + 1), v->pair_first[code], v->pair_count[code]);
+                                  code % (DG_VARP_MAXN + 1), v->pair_first[code], v->pair_count[code], from_traces);
       if (err) return err;
     }
     if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
@@ -178,7 +183,8 @@ int launch_all(dg_varp* v, const double* Qin, double* Qout, double* RR, int mode
     if (err) return err;
     for (int nc = 1; nc <= DG_VARP_MAXN; ++nc) {
       if (!v->hang_count[nc]) continue;
-      err = dg_launch_varp_hanging(v->stream, v->tab[1][0], m, Qin, nc, v->hang_first[nc], v->hang_count[nc]);
+      err = dg_launch_varp_hanging(v->stream, v->tab[1][0], m, Qin, nc, v->hang_first[nc], v->hang_count[nc],
+                                   from_traces);
       if (err) return err;
     }
     if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
@@ -189,7 +195,7 @@ int launch_all(dg_varp* v, const double* Qin, double* Qout, double* RR, int mode
       Timed* tm = timer(v, 3 * (N - 1) + mode, &err);
       if (err) return err;
       err = dg_launch_varp(v->stream, N, v->tab[N][lev], m, v->first[N][lev], v->count[N][lev], Qin, Qout, RR, mode,
-                           a, b, dt);
+                           a, b, dt, traces);
       if (err) return err;
       if (tm && (err = (int)hipEventRecord(tm->b, v->stream))) return err;
     }
@@ -529,7 +535,7 @@ int dg_varp_rhs(dg_varp* v, const double* Q, double* R) {
   if (rc) return rc;
   rc = check_pair(v, Q, "Q", R, "R");
   if (rc) return rc;
-  const int err = launch_all(v, Q, nullptr, R, 0, 0.0, 0.0, 0.0);
+  const int err = launch_all(v, Q, nullptr, R, 0, 0.0, 0.0, 0.0, false, false);
   if (err) return hipfail(err, "variable-degree rhs launch");
   return DG_OK;
 }
@@ -542,10 +548,15 @@ int dg_varp_rk_steps(dg_varp* v, double* Q, double* res, double dt, int nsteps) 
   if (nsteps < 0) return dg_set_error(DG_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(dt)) return dg_set_error(DG_EINVAL, "dt not finite");
   double* buf[2] = {Q, (double*)(v->ws + layout(v).off_q2)};
+  // the first stage's face launches form the traces of Q from its state;
+  // every stage launch writes the traces of its output for the next stage
+  const bool faces = !v->faces.empty() || !v->hangs.empty();
   for (int n = 0; n < nsteps; ++n) {
     for (int s = 0; s < 5; ++s) {
       const int g = (n & 1) + s;
-      const int err = launch_all(v, buf[g & 1], buf[(g + 1) & 1], res, s == 0 ? 2 : 1, kDgRKA[s], kDgRKB[s], dt);
+      const bool first = n == 0 && s == 0, last = n == nsteps - 1 && s == 4;
+      const int err = launch_all(v, buf[g & 1], buf[(g + 1) & 1], res, s == 0 ? 2 : 1, kDgRKA[s], kDgRKB[s], dt,
+                                 faces && !first, faces && !last);
       if (err) return hipfail(err, "variable-degree stage launch");
     }
   }
