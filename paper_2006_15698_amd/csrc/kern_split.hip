@@ -52,6 +52,10 @@ struct SCfg {
   // registers, and spilled)
   static constexpr int NF = WAVES ? 3 * WPD * 64 : 6 * N2;
   static constexpr int NT = ((N3 > NF ? N3 : NF) + 63) / 64 * 64;
+  // the element's state in LDS for its own face traces (at N = 8 the 20 KB
+  // would leave one workgroup per CU: there the traces read global memory)
+  static constexpr bool QL = N < 8;
+  static constexpr int NQ = QL ? N3 : 1;
 };
 
 // Primitive description of a state: rho, u, v, w, p, e = E / rho.
@@ -163,14 +167,15 @@ __device__ __forceinline__ void face_line_sum(const double (*P)[6], const Prim& 
 }
 
 // Face point i (side s = i / N^2, point pt) of direction D: the element's own
-// trace and its neighbour's (interpolated from their states along the normal
-// line), the Lax-Friedrichs flux, and into LDS the point's G term and its
+// trace (from its state in LDS; from global memory at N = 8) and its
+// neighbour's (from global memory), each interpolated along the normal line,
+// the Lax-Friedrichs flux, and into LDS the point's G term and its
 // own trace's primitives.  The side is a per-lane select, so lanes of both
 // sides of a direction run the same instructions.
 template <int N, int D>
 __device__ __forceinline__ void split_face(const DGTables& tb, const double* __restrict__ Qin, int64_t fs, int e,
-                                           int i, const double (*P)[6], double (*Tp)[SCfg<N>::N2][6],
-                                           double (*G)[SCfg<N>::N2][6]) {
+                                           int i, const double (*Qs)[SCfg<N>::NQ], const double (*P)[6],
+                                           double (*Tp)[SCfg<N>::N2][6], double (*G)[SCfg<N>::N2][6]) {
   constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3;
   const int s = i / N2, pt = i - s * N2;
   const int face = 2 * D + s;
@@ -185,7 +190,7 @@ __device__ __forceinline__ void split_face(const DGTables& tb, const double* __r
     const double wn = s ? tb.lm[m] : tb.lp[m];   // the neighbour's trace on its opposite face
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      own[f] = fma(wo, qe[f * fs + node], own[f]);
+      own[f] = fma(wo, SCfg<N>::QL ? Qs[f][SCfg<N>::QL ? node : 0] : qe[f * fs + node], own[f]);
       nbr[f] = fma(wn, qn[f * fs + node], nbr[f]);
     }
   }
@@ -216,6 +221,7 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
   __shared__ __align__(16) double P[N3][6];        // node primitives
   __shared__ __align__(16) double Tp[6][N2][6];    // own trace primitives per face (2d + side)
   __shared__ __align__(16) double G[6][N2][6];     // per face point: Lax-Friedrichs flux - sum_a l_a f_S(Q~_f, Q_a)
+  __shared__ double Qs[5][SCfg<N>::NQ];             // the element's state (its own face traces)
   __shared__ double Dm[N][N];        // D_ia = l_a'(xi_i)
   // the element of this workgroup in the visiting order (pencils, XCD chunks)
   int e, ne;
@@ -232,7 +238,10 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
   if (t < N3) {
     double q[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) q[f] = qe[f * fs + t];
+    for (int f = 0; f < 5; ++f) {
+      q[f] = qe[f * fs + t];
+      if (SCfg<N>::QL) Qs[f][SCfg<N>::QL ? t : 0] = q[f];
+    }
     const Prim s = to_prim(q, tb.gm1);
     lds_put(P[t], s);
   }
@@ -243,9 +252,9 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
     const int d = SCfg<N>::WAVES ? wave / WPD : t / (2 * N2);
     const int fi = SCfg<N>::WAVES ? (wave - d * WPD) * 64 + lane : t - d * 2 * N2;
     if (d < 3 && fi < 2 * N2) {
-      if (d == 0) split_face<N, 0>(tb, Qin, fs, e, fi, P, Tp, G);
-      else if (d == 1) split_face<N, 1>(tb, Qin, fs, e, fi, P, Tp, G);
-      else split_face<N, 2>(tb, Qin, fs, e, fi, P, Tp, G);
+      if (d == 0) split_face<N, 0>(tb, Qin, fs, e, fi, Qs, P, Tp, G);
+      else if (d == 1) split_face<N, 1>(tb, Qin, fs, e, fi, Qs, P, Tp, G);
+      else split_face<N, 2>(tb, Qin, fs, e, fi, Qs, P, Tp, G);
     }
   }
   __syncthreads();

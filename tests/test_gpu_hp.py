@@ -5,7 +5,8 @@ single-degree library on the twice finer mesh; random refinements with
 mixed degrees 0..7 element by element, three LSERK45 steps, conservation
 across hanging faces, meshes one to three cells across, the Taylor-Green
 hp workload (40^3 cells, enstrophy-driven refinement and degrees 3..5) on
-sampled cells, and the argument checks."""
+sampled cells, the face traces written by the stage kernels against those
+formed from the state (bitwise), and the argument checks."""
 
 import numpy as np
 import pytest
@@ -301,3 +302,26 @@ def test_argument_checks_refined(dgm):
         dgm.VariableDegree((2, 1, 1), [1] * 8 + [8], refine=[1, 0])
     v = dgm.VariableDegree((2, 1, 1), [0] * 8 + [2], refine=[1, 0])
     assert v.E == 9 and v.num_dof() == 8 + 27
+
+
+@pytest.mark.parametrize("refined", [False, True])
+def test_stage_traces_equal_traces_from_the_state(dgm, refined):
+    """Within one call the face kernels read the traces that the previous
+    stage's kernels wrote; the first stage of a call forms them from the
+    state.  Three steps in one call and three calls of one step therefore
+    take the two routes at the starts of steps 2 and 3, and must agree bit
+    for bit (state and residual)."""
+    import torch
+    n, L = (4, 3, 3), (1.0, 0.9, 1.1)
+    ref = W.random_refinement(n, 0.4, 790) if refined else np.zeros((n[2], n[1], n[0]), dtype=np.int64)
+    deg = np.random.default_rng(791).integers(1, 6, _n_elem(ref))
+    print(f"[hp traces refined={refined}]", flush=True)
+    Q0 = W.hp_state(n, ref, deg, _smooth, L=L)
+    v = dgm.VariableDegree(n, deg, L=L, refine=ref)
+    dt = RefinedMeshDG(n, ref, deg, L=L).dt_cfl(Q0, 0.3)
+    Qa, Qb = _dev(Q0), _dev(Q0)
+    ra, rb = torch.zeros_like(Qa), torch.zeros_like(Qb)
+    v.step(Qa, ra, dt, nsteps=3)
+    for _ in range(3):
+        v.step(Qb, rb, dt, nsteps=1)
+    assert torch.equal(Qa, Qb) and torch.equal(ra, rb)
