@@ -58,7 +58,9 @@ struct SCfg {
   static constexpr int NQ = QL ? N3 : 1;
 };
 
-// Primitive description of a state: rho, u, v, w, p, e = E / rho.
+// Half the primitives of a state: rho, u, v, w, p, e = E / rho, each times
+// 1/2, so that the mean of two states' values is one addition (halving is
+// exact, so a/2 + b/2 is (a + b)/2 bit for bit).
 struct Prim {
   double r, u[3], p, e;
 };
@@ -66,28 +68,29 @@ struct Prim {
 __device__ __forceinline__ Prim to_prim(const double* q, double gm1) {
   Prim s;
   const double ri = dgdev::recip(q[0]);
-  s.r = q[0];
-  s.u[0] = q[1] * ri;
-  s.u[1] = q[2] * ri;
-  s.u[2] = q[3] * ri;
-  s.p = gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * ri);
-  s.e = q[4] * ri;
+  s.r = 0.5 * q[0];
+  s.u[0] = 0.5 * (q[1] * ri);
+  s.u[1] = 0.5 * (q[2] * ri);
+  s.u[2] = 0.5 * (q[3] * ri);
+  s.p = 0.5 * (gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * ri));
+  s.e = 0.5 * (q[4] * ri);
   return s;
 }
 
-// Kennedy-Gruber two-point flux in direction D, accumulated with weight c.
+// Kennedy-Gruber two-point flux in direction D of two states given by their
+// half primitives, accumulated with weight c.
 template <int D>
 __device__ __forceinline__ void kg_acc(const Prim& a, const Prim& b, double c, double* acc) {
-  const double rho = 0.5 * (a.r + b.r);
-  const double ud = 0.5 * (a.u[D] + b.u[D]);
-  const double pm = 0.5 * (a.p + b.p);
+  const double rho = a.r + b.r;
+  const double ud = a.u[D] + b.u[D];
+  const double pm = a.p + b.p;
   const double mass = rho * ud;
   double f[5];
   f[0] = mass;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) f[1 + k] = mass * (0.5 * (a.u[k] + b.u[k]));
+  for (int k = 0; k < 3; ++k) f[1 + k] = mass * (a.u[k] + b.u[k]);
   f[1 + D] += pm;
-  f[4] = mass * (0.5 * (a.e + b.e)) + pm * ud;
+  f[4] = mass * (a.e + b.e) + pm * ud;
 #pragma unroll
   for (int v = 0; v < 5; ++v) acc[v] = fma(c, f[v], acc[v]);
 }
