@@ -78,19 +78,25 @@ __device__ __forceinline__ Prim to_prim(const double* q, double gm1) {
 }
 
 // Kennedy-Gruber two-point flux in direction D of two states given by their
-// half primitives, accumulated with weight c.
+// half primitives.
 template <int D>
-__device__ __forceinline__ void kg_acc(const Prim& a, const Prim& b, double c, double* acc) {
+__device__ __forceinline__ void kg_flux(const Prim& a, const Prim& b, double* f) {
   const double rho = a.r + b.r;
   const double ud = a.u[D] + b.u[D];
   const double pm = a.p + b.p;
   const double mass = rho * ud;
-  double f[5];
   f[0] = mass;
 #pragma unroll
   for (int k = 0; k < 3; ++k) f[1 + k] = mass * (a.u[k] + b.u[k]);
   f[1 + D] += pm;
   f[4] = mass * (a.e + b.e) + pm * ud;
+}
+
+// The same, accumulated with weight c.
+template <int D>
+__device__ __forceinline__ void kg_acc(const Prim& a, const Prim& b, double c, double* acc) {
+  double f[5];
+  kg_flux<D>(a, b, f);
 #pragma unroll
   for (int v = 0; v < 5; ++v) acc[v] = fma(c, f[v], acc[v]);
 }
@@ -119,37 +125,36 @@ __device__ __forceinline__ void lds_put(double* p, const Prim& s) {
 
 // Volume and face terms of direction D for node (m0 along the line, pt
 // across it) of the element whose node primitives are P, accumulated (with
-// the -(2/h_D) factor) into out.  G holds, per face point, the part of the
-// face term that does not depend on the node along the line:
-// F*_f - sum_a l_a(f) f_S(Q~_f, Q_a).
+// the -(2/h_D) factor) into out.  The two face terms' sums over the line
+// enter linearly, so they fold into the volume weights:
+//   W_ia = 2 D_ia - l_i(+1)/w_i l_a(+1) + l_i(-1)/w_i l_a(-1),
+//   rate_i = sum_a W_ia f_S(Q_i, Q_a) + l_i(+1)/w_i (f_S(Q_i, Q~_+) + G_+)
+//            - l_i(-1)/w_i (f_S(Q_i, Q~_-) + G_-),
+// G holding, per face point, the part of the face term that does not depend
+// on the node along the line: F*_f - sum_a l_a(f) f_S(Q~_f, Q_a).
 template <int N, int D>
-__device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)[6], const double (*Dm)[N],
+__device__ __forceinline__ void split_line(const DGTables& tb, const double (*P)[6], const double (*Wm)[N],
                                            const double (*Tp)[SCfg<N>::N2][6], const double (*G)[SCfg<N>::N2][6],
                                            int m0, int pt, double* out) {
   const Prim si = lds_prim(P[dgdev::tnode<N>(D, m0, pt)]);
-  double vol[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum_a 2 D_ia f_S(Q_i, Q_a)
-  double em[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(-1) f_S(Q_i, Q_a)
-  double ep[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // sum_a l_a(+1) f_S(Q_i, Q_a)
+  double vol[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum_a W_ia f_S(Q_i, Q_a)
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     const Prim sa = lds_prim(P[dgdev::tnode<N>(D, a, pt)]);
-    double f[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    kg_acc<D>(si, sa, 1.0, f);
+    double f[5];
+    kg_flux<D>(si, sa, f);
+    const double w = Wm[m0][a];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      vol[v] = fma(2.0 * Dm[m0][a], f[v], vol[v]);
-      em[v] = fma(tb.lm[a], f[v], em[v]);
-      ep[v] = fma(tb.lp[a], f[v], ep[v]);
-    }
+    for (int v = 0; v < 5; ++v) vol[v] = fma(w, f[v], vol[v]);
   }
   double br[2][5];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const Prim tf = lds_prim(Tp[2 * D + s][pt]);
-    double fi[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    kg_acc<D>(si, tf, 1.0, fi);                  // f_S(Q_i, Q~_f)
+    double fi[5];
+    kg_flux<D>(si, tf, fi);                      // f_S(Q_i, Q~_f)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) br[s][v] = fi[v] - (s ? ep[v] : em[v]) + G[2 * D + s][pt][v];
+    for (int v = 0; v < 5; ++v) br[s][v] = fi[v] + G[2 * D + s][pt][v];
   }
   const double sc = tb.sc[D];
 #pragma unroll
@@ -225,7 +230,7 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
   __shared__ __align__(16) double Tp[6][N2][6];    // own trace primitives per face (2d + side)
   __shared__ __align__(16) double G[6][N2][6];     // per face point: Lax-Friedrichs flux - sum_a l_a f_S(Q~_f, Q_a)
   __shared__ double Qs[5][SCfg<N>::NQ];             // the element's state (its own face traces)
-  __shared__ double Dm[N][N];        // D_ia = l_a'(xi_i)
+  __shared__ double Wm[N][N];        // W_ia = 2 D_ia - l_i(1) l_a(1) / w_i + l_i(-1) l_a(-1) / w_i
   // the element of this workgroup in the visiting order (pencils, XCD chunks)
   int e, ne;
   dgdev::block_elements<1>(tb, ord, blockIdx.x, gridDim.x, e, ne);
@@ -236,7 +241,8 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
   if (t < N2) {
     const int i = t / N, aa = t % N;
     // Dh[a N + i] = w_i l_a'(xi_i) / w_a
-    Dm[i][aa] = tb.Dh[aa * N + i] * tb.w[aa] / tb.w[i];
+    const double dia = tb.Dh[aa * N + i] * tb.w[aa] / tb.w[i];   // D_ia = l_a'(xi_i)
+    Wm[i][aa] = 2.0 * dia - tb.liftp[i] * tb.lp[aa] + tb.liftm[i] * tb.lm[aa];
   }
   if (t < N3) {
     double q[5];
@@ -264,9 +270,9 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
   if (t >= N3) return;
   const int i = t % N, j = (t / N) % N, k = t / N2;
   double rate[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  split_line<N, 0>(tb, P, Dm, Tp, G, i, j + N * k, rate);
-  split_line<N, 1>(tb, P, Dm, Tp, G, j, i + N * k, rate);
-  split_line<N, 2>(tb, P, Dm, Tp, G, k, i + N * j, rate);
+  split_line<N, 0>(tb, P, Wm, Tp, G, i, j + N * k, rate);
+  split_line<N, 1>(tb, P, Wm, Tp, G, j, i + N * k, rate);
+  split_line<N, 2>(tb, P, Wm, Tp, G, k, i + N * j, rate);
   const int64_t g = (int64_t)e * N3 + t;
   if (MODE == 0) {
 #pragma unroll
