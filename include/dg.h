@@ -415,8 +415,11 @@ int64_t dg_varp_num_elements(const dg_varp* v);
 int64_t dg_varp_offset(const dg_varp* v, int64_t e);
 size_t dg_varp_workspace_bytes(const dg_varp* v);
 /* Caller-owned device workspace (256-byte aligned): mortar tables, face
- * table, offsets, element lists, the face-flux buffer and the second state
- * buffer of the ping-pong.  SYNCHRONISING (uploads the tables). */
+ * table, offsets, element lists, the face-flux buffer, the face-trace buffer
+ * (the elements' traces on those faces, which each stage of
+ * dg_varp_rk_steps writes for the next) and the second state buffer of the
+ * ping-pong.  Calls on one context share it: they must not overlap.
+ * SYNCHRONISING (uploads the tables). */
 int dg_varp_set_workspace(dg_varp* v, void* dptr, size_t bytes);
 /* R = dQ/dt. */
 int dg_varp_rhs(dg_varp* v, const double* Q, double* R);
