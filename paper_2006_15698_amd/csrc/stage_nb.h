@@ -168,16 +168,20 @@ struct RowPairLane {
     b = r / RL;
     c = r - b * RL;
   }
-  // first point of the node pair this lane loads, and which of the two is its own
-  __host__ __device__ int pair_start() const { return ((c & ~1) < N - 1 ? (c & ~1) : N - 2) + N * b; }
-  __host__ __device__ int own() const { return (c < N ? c : N - 1) + N * b - pair_start(); }
+  // first point of the node pair this lane loads (its own point is half
+  // c & 1 of the pair; the last pair of a row reaches one node past the row,
+  // which for the line positions m <= N - 2 that are loaded in pairs is still
+  // a node of the element)
+  __host__ __device__ int pair_start() const { return (c & ~1) + N * b; }
+  // the lane's own point (the phantom lane: the last point of its row)
+  __host__ __device__ int own_point() const { return (c < N ? c : N - 1) + N * b; }
 };
 
 // chunk_trace for odd N on the row-pair layout: each lane loads the node
-// pair of its row pair at m = 2j + (c & 1) (j < (N - 1) / 2) and at
-// m = N - 1, takes its value at the other m of each two from its partner by
-// DPP, and keeps its own half of the pair.  Same FMA chain as chunk_trace.
-// Both lanes of a pair must be active.
+// pair of its row pair at m = 2j + s (s = c & 1, j < (N - 1) / 2), sends its
+// partner the half that is the partner's point (a select, then one DPP
+// swap), and loads its own point at m = N - 1 alone.  Same FMA chain as
+// chunk_trace.  Both lanes of a pair must be active.
 template <int N, int EPB, int D, int SIDE>
 __device__ __forceinline__ void chunk_trace_rp(const double* __restrict__ base, int64_t EN3,
                                                const RowPairLane<N, EPB>& rp, const double* lmr,
@@ -186,29 +190,29 @@ __device__ __forceinline__ void chunk_trace_rp(const double* __restrict__ base, 
   constexpr int N3 = N * N * N, J = (N - 1) / 2;
   const int s = rp.c & 1;
   const int p0 = rp.pair_start();
-  const int k = rp.own();
-  double2 w[5][J + 1];
+  const int po = rp.own_point();
+  double2 w[5][J];
+  double wl[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
-    const double* qn = base + f * EN3 + rp.fel * N3 + tnode<N>(D, 0, p0);
+    const double* qn = base + f * EN3 + rp.fel * N3;
 #pragma unroll
-    for (int j = 0; j <= J; ++j) {
-      const int m = j < J ? 2 * j + s : N - 1;
-      __builtin_memcpy(&w[f][j], qn + (tnode<N>(D, m, p0) - tnode<N>(D, 0, p0)), 16);
-    }
+    for (int j = 0; j < J; ++j) __builtin_memcpy(&w[f][j], qn + tnode<N>(D, 2 * j + s, p0), 16);
+    wl[f] = qn[tnode<N>(D, N - 1, po)];
   }
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     double v = 0.0;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const double px = swap_adjacent(w[f][j].x), py = swap_adjacent(w[f][j].y);
-      const double mine = k ? w[f][j].y : w[f][j].x;     // own point at m = 2j + s
-      const double other = k ? py : px;                   // own point at the partner's m
-      v = fma(SIDE ? lmr[2 * j] : lpr[2 * j], s ? other : mine, v);
-      v = fma(SIDE ? lmr[2 * j + 1] : lpr[2 * j + 1], s ? mine : other, v);
+      // the pair holds both lanes' points (this lane's is half s): each lane
+      // sends the partner's half, so `other` is this lane's point at the
+      // partner's m
+      const double other = swap_adjacent(s ? w[f][j].x : w[f][j].y);
+      v = fma(SIDE ? lmr[2 * j] : lpr[2 * j], s ? other : w[f][j].x, v);
+      v = fma(SIDE ? lmr[2 * j + 1] : lpr[2 * j + 1], s ? w[f][j].y : other, v);
     }
-    v = fma(SIDE ? lmr[N - 1] : lpr[N - 1], k ? w[f][J].y : w[f][J].x, v);
+    v = fma(SIDE ? lmr[N - 1] : lpr[N - 1], wl[f], v);
     out[f] = v;
   }
 }

@@ -80,10 +80,12 @@ static int check_x2() {
 }
 
 // Row-pair layout (RowPairLane, odd N): lanes 2k and 2k + 1 share element
-// and row and load the same node pair, which lies in that row; the real
-// lanes (c < N) cover every point of the face chunk exactly once, each
-// owning one half of its pair; and the pair's line nodes are neighbours in
-// memory inside the element for every m.
+// and row and load the same node pair, starting at the even point of the
+// pair's two lanes; the real lanes (c < N) cover every point of the face
+// chunk exactly once, each owning half c & 1 of its pair; and for every line
+// position m <= N - 2 (the ones loaded in pairs) the pair's line nodes are
+// neighbours in memory inside the element (the last pair of a row reaches
+// one node past the row).
 template <int N, int EPB>
 static int check_rp() {
   using RP = dgdev::RowPairLane<N, EPB>;
@@ -100,27 +102,28 @@ static int check_rp() {
       return 1;
     }
     const int ps = p0.pair_start();
-    if (ps - N * p0.b < 0 || ps - N * p0.b + 1 >= N) {
-      printf("N=%d EPB=%d lane %d: pair leaves its row\n", N, EPB, lane);
+    if (ps - N * p0.b < 0 || ps - N * p0.b > N - 1) {
+      printf("N=%d EPB=%d lane %d: pair does not start in its row\n", N, EPB, lane);
       return 1;
     }
     for (int d = 1; d <= 2; ++d) {
-      for (int m = 0; m < N; ++m) {
+      for (int m = 0; m + 1 < N; ++m) {
         const int n0 = d == 1 ? dgdev::tnode<N>(1, m, ps) : dgdev::tnode<N>(2, m, ps);
-        const int n1 = d == 1 ? dgdev::tnode<N>(1, m, ps + 1) : dgdev::tnode<N>(2, m, ps + 1);
-        if (n1 != n0 + 1 || n0 < 0 || n1 >= N3) {
-          printf("N=%d EPB=%d d=%d lane %d m %d: nodes not adjacent\n", N, EPB, d, lane, m);
+        const int n1 = n0 + 1;
+        if (n0 < 0 || n1 >= N3) {
+          printf("N=%d EPB=%d d=%d lane %d m %d: pair outside the element\n", N, EPB, d, lane, m);
           return 1;
         }
       }
     }
     for (const RP* p : {&p0, &p1}) {
-      if (p->own() < 0 || p->own() > 1) {
-        printf("N=%d EPB=%d: own half out of range\n", N, EPB);
+      const int op = p->own_point();
+      if (op - N * p->b < 0 || op - N * p->b > N - 1) {
+        printf("N=%d EPB=%d: own point outside its row\n", N, EPB);
         return 1;
       }
       if (p->c < N) {
-        if (ps + p->own() != p->c + N * p->b) {
+        if (ps + (p->c & 1) != p->c + N * p->b || op != p->c + N * p->b) {
           printf("N=%d EPB=%d: lane's own half is not its point\n", N, EPB);
           return 1;
         }
