@@ -304,8 +304,8 @@ def test_argument_checks_refined(dgm):
     assert v.E == 9 and v.num_dof() == 8 + 27
 
 
-@pytest.mark.parametrize("refined", [False, True])
-def test_stage_traces_equal_traces_from_the_state(dgm, refined):
+@pytest.mark.parametrize("refined,pmin,pmax", [(False, 1, 5), (True, 1, 5), (False, 0, 7), (True, 0, 7)])
+def test_stage_traces_equal_traces_from_the_state(dgm, refined, pmin, pmax):
     """Within one call the face kernels read the traces that the previous
     stage's kernels wrote; the first stage of a call forms them from the
     state.  Three steps in one call and three calls of one step therefore
@@ -314,8 +314,8 @@ def test_stage_traces_equal_traces_from_the_state(dgm, refined):
     import torch
     n, L = (4, 3, 3), (1.0, 0.9, 1.1)
     ref = W.random_refinement(n, 0.4, 790) if refined else np.zeros((n[2], n[1], n[0]), dtype=np.int64)
-    deg = np.random.default_rng(791).integers(1, 6, _n_elem(ref))
-    print(f"[hp traces refined={refined}]", flush=True)
+    deg = np.random.default_rng(791 + pmax).integers(pmin, pmax + 1, _n_elem(ref))
+    print(f"[hp traces refined={refined} degrees {pmin}..{pmax}]", flush=True)
     Q0 = W.hp_state(n, ref, deg, _smooth, L=L)
     v = dgm.VariableDegree(n, deg, L=L, refine=ref)
     dt = RefinedMeshDG(n, ref, deg, L=L).dt_cfl(Q0, 0.3)
