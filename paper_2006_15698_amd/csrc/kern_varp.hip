@@ -20,15 +20,17 @@
 // face against four fine ones takes the sum of the four quarters'
 // projections.
 //
-// k_varp_mortar<NLO, NHI>: one launch per degree pair, one wave per face
-//   between those degrees (same size): the lower-degree side's trace at its face nodes into
-//   LDS, the higher side's trace at its face nodes (the mortar points) in
-//   registers, the lower side's trace interpolated to the mortar points, the
-//   flux, written for the higher side and projected for the lower side into
-//   the face-flux buffer.
+// k_varp_mortar<NLO, NHI, FT>: one launch per degree pair, one wave per face
+//   between those degrees (same size): the lower-degree side's trace at its
+//   face nodes into LDS, the higher side's trace at its face nodes (the
+//   mortar points) in registers (both from the states along the normal
+//   lines, or, FT, as the previous stage's launches wrote them into the
+//   face-trace buffer), the lower side's trace interpolated to the mortar
+//   points, the flux, written for the higher side and projected for the
+//   lower side into the face-flux buffer.
 // k_varp_hanging (kern_varp_hang.hip): one workgroup per coarse face with
 //   hanging faces, one wave per quarter.
-// k_varp<N, MODE>: a workgroup owns EPB elements of one degree and size from
+// k_varp<N, MODE, TR>: a workgroup owns EPB elements of one degree and size from
 // that group's element list (in pencil order; each XCD takes a contiguous
 // part), one thread per node:
 //   A. the elements' states into LDS (each element's nodes are contiguous);
@@ -40,7 +42,10 @@
 //      projected flux from the buffer;
 //   C/D. the volume contraction, lift and RK update of the single-degree
 //      neighbour-read kernel, in the same order, so that a mesh of one degree
-//      and size gives bitwise the results of that kernel.
+//      and size gives bitwise the results of that kernel;
+//   E. (TR, workgroups with a face that takes its flux from the buffer) the
+//      new state into LDS and its traces on those faces into the face-trace
+//      buffer, at the faces' flux places, for the next stage's face launches.
 // State layout: Q[f * T + off[e] + (k N + j) N + i], T the total node count.
 
 #include "dg_varp.h"
