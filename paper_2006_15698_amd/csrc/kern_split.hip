@@ -56,6 +56,12 @@ struct SCfg {
   // would leave one workgroup per CU: there the traces read global memory)
   static constexpr bool QL = N < 8;
   static constexpr int NQ = QL ? N3 : 1;
+  // the neighbour's face traces formed while the node primitives are staged
+  // (their loads overlap the staging), and the update's state taken from
+  // LDS; at N = 7 either costs registers (the update 150 -> 168 VGPRs, the
+  // early traces spills) and time, so there the traces follow the staging
+  // and the update reads global memory
+  static constexpr bool EARLY = N != 7;
 };
 
 // Half the primitives of a state: rho, u, v, w, p, e = E / rho, each times
@@ -174,23 +180,47 @@ __device__ __forceinline__ void face_line_sum(const double (*P)[6], const Prim& 
   }
 }
 
-// Face point i (side s = i / N^2, point pt) of direction D: the element's own
-// trace (from its state in LDS; from global memory at N = 8) and its
-// neighbour's (from global memory), each interpolated along the normal line,
-// the Lax-Friedrichs flux, and into LDS the point's G term and its
-// own trace's primitives.  The side is a per-lane select, so lanes of both
-// sides of a direction run the same instructions.
+// The neighbour's trace at face point i (side s = i / N^2, point pt) of
+// direction D, interpolated along its normal line from global memory (no
+// shared memory: issued before the node primitives are staged).
 template <int N, int D>
-__device__ __forceinline__ void split_face(const DGTables& tb, const double* __restrict__ Qin, int64_t fs, int e,
-                                           int i, const double (*Qs)[SCfg<N>::NQ], const double (*P)[6],
-                                           double (*Tp)[SCfg<N>::N2][6], double (*G)[SCfg<N>::N2][6]) {
+__device__ __forceinline__ void nbr_trace(const DGTables& tb, const double* __restrict__ Qin, int64_t fs, int e,
+                                          int i, double* nbr) {
   constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3;
   const int s = i / N2, pt = i - s * N2;
-  const int face = 2 * D + s;
   const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, D, s ? 1 : -1);
-  const double* qe = Qin + (int64_t)e * N3;
   const double* qn = Qin + (int64_t)en * N3;
-  double own[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, nbr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int f = 0; f < 5; ++f) nbr[f] = 0.0;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int node = dgdev::tnode<N>(D, m, pt);
+    const double wn = s ? tb.lm[m] : tb.lp[m];   // the neighbour's trace on its opposite face
+#pragma unroll
+    for (int f = 0; f < 5; ++f) nbr[f] = fma(wn, qn[f * fs + node], nbr[f]);
+  }
+}
+
+// Face point i of direction D: the element's own trace (from its state in
+// LDS; from global memory at N = 8), the neighbour's (given, or with EARLY
+// off interpolated here beside the own trace), the Lax-Friedrichs flux, and
+// into LDS the point's G term and its own trace's primitives.  The side is a
+// per-lane select, so lanes of both sides of a direction run the same
+// instructions.
+template <int N, int D>
+__device__ __forceinline__ void split_face(const DGTables& tb, const double* __restrict__ Qin, int64_t fs, int e,
+                                           int i, const double* nbr_in, const double (*Qs)[SCfg<N>::NQ],
+                                           const double (*P)[6], double (*Tp)[SCfg<N>::N2][6],
+                                           double (*G)[SCfg<N>::N2][6]) {
+  constexpr int N2 = SCfg<N>::N2, N3 = SCfg<N>::N3;
+  constexpr bool EARLY = SCfg<N>::EARLY;
+  const int s = i / N2, pt = i - s * N2;
+  const int face = 2 * D + s;
+  const double* qe = Qin + (int64_t)e * N3;
+  const double* qn = Qin + (int64_t)(EARLY ? 0 : dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, D, s ? 1 : -1)) * N3;
+  double own[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, nbr[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) nbr[f] = EARLY ? nbr_in[f] : 0.0;
 #pragma unroll
   for (int m = 0; m < N; ++m) {
     const int node = dgdev::tnode<N>(D, m, pt);
@@ -199,7 +229,7 @@ __device__ __forceinline__ void split_face(const DGTables& tb, const double* __r
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
       own[f] = fma(wo, SCfg<N>::QL ? Qs[f][SCfg<N>::QL ? node : 0] : qe[f * fs + node], own[f]);
-      nbr[f] = fma(wn, qn[f * fs + node], nbr[f]);
+      if (!EARLY) nbr[f] = fma(wn, qn[f * fs + node], nbr[f]);
     }
   }
   // the face's -d side state first
@@ -244,27 +274,35 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
     const double dia = tb.Dh[aa * N + i] * tb.w[aa] / tb.w[i];   // D_ia = l_a'(xi_i)
     Wm[i][aa] = 2.0 * dia - tb.liftp[i] * tb.lp[aa] + tb.liftm[i] * tb.lm[aa];
   }
+  // face points: wave w < 3 WPD takes 64 points of direction w / WPD (or,
+  // below N = 5, thread t takes point t); the neighbour's trace needs no
+  // shared memory, so its loads can be issued with the element's own
+  const int d = SCfg<N>::WAVES ? wave / WPD : t / (2 * N2);
+  const int fi = SCfg<N>::WAVES ? (wave - d * WPD) * 64 + lane : t - d * 2 * N2;
+  const bool fpt = d < 3 && fi < 2 * N2;
+  double q[5], nbr[5];
   if (t < N3) {
-    double q[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      q[f] = qe[f * fs + t];
-      if (SCfg<N>::QL) Qs[f][SCfg<N>::QL ? t : 0] = q[f];
+    for (int f = 0; f < 5; ++f) q[f] = qe[f * fs + t];
+  }
+  if (SCfg<N>::EARLY && fpt) {
+    if (d == 0) nbr_trace<N, 0>(tb, Qin, fs, e, fi, nbr);
+    else if (d == 1) nbr_trace<N, 1>(tb, Qin, fs, e, fi, nbr);
+    else nbr_trace<N, 2>(tb, Qin, fs, e, fi, nbr);
+  }
+  if (t < N3) {
+    if (SCfg<N>::QL) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) Qs[f][SCfg<N>::QL ? t : 0] = q[f];
     }
     const Prim s = to_prim(q, tb.gm1);
     lds_put(P[t], s);
   }
   __syncthreads();   // the face phase reads the node primitives
-  // face points: wave w < 3 WPD takes 64 points of direction w / WPD (or,
-  // below N = 5, thread t takes point t)
-  {
-    const int d = SCfg<N>::WAVES ? wave / WPD : t / (2 * N2);
-    const int fi = SCfg<N>::WAVES ? (wave - d * WPD) * 64 + lane : t - d * 2 * N2;
-    if (d < 3 && fi < 2 * N2) {
-      if (d == 0) split_face<N, 0>(tb, Qin, fs, e, fi, Qs, P, Tp, G);
-      else if (d == 1) split_face<N, 1>(tb, Qin, fs, e, fi, Qs, P, Tp, G);
-      else split_face<N, 2>(tb, Qin, fs, e, fi, Qs, P, Tp, G);
-    }
+  if (fpt) {
+    if (d == 0) split_face<N, 0>(tb, Qin, fs, e, fi, nbr, Qs, P, Tp, G);
+    else if (d == 1) split_face<N, 1>(tb, Qin, fs, e, fi, nbr, Qs, P, Tp, G);
+    else split_face<N, 2>(tb, Qin, fs, e, fi, nbr, Qs, P, Tp, G);
   }
   __syncthreads();
   if (t >= N3) return;
@@ -282,7 +320,7 @@ k_split(DGTables tb, const double* __restrict__ Qin, double* __restrict__ Qout, 
     for (int f = 0; f < 5; ++f) {
       const double r = MODE == 2 ? dt * rate[f] : fma(a, RR[f * fs + g], dt * rate[f]);
       RR[f * fs + g] = r;
-      Qout[f * fs + g] = fma(b, r, Qin[f * fs + g]);
+      Qout[f * fs + g] = fma(b, r, SCfg<N>::QL && SCfg<N>::EARLY ? Qs[f][SCfg<N>::QL ? t : 0] : Qin[f * fs + g]);
     }
   }
 }
