@@ -66,10 +66,12 @@ WORKLOADS = {
 # Viscous workloads: (dynamic viscosity, Prandtl number).
 VISCOUS = {"tgv48_p4_re1600": (1.0 / 1600.0, 0.71)}
 # Bytes per node and stage of the viscous decomposition (FP64, 5 fields, 12
-# viscous-flux values): the inviscid rate (read Q, write R) 80; k_visc_flux
-# (read Q, write the flux) 136; k_visc_apply (read the flux, R, Q, res; write
-# Q, res) 296.
+# viscous-flux values).  Fused (default): k_visc_flux forms the inviscid rate
+# too (read Q, write the flux and R) 176; k_visc_apply (read the flux, R, Q,
+# res; write Q, res) 296.  Separate: the inviscid rate (read Q, write R) 80,
+# k_visc_flux (read Q, write the flux) 136, k_visc_apply 296.
 VISC_BYTES = {"rhs": 80, "visc": 136 + 296}
+VISC_BYTES_FUSED = {"visc": 176 + 296}
 # Workloads on the split-form volume term (DG_VOLUME_KEP).
 SPLIT_FORM = {"tgv48_p4_kep"}
 
@@ -836,30 +838,38 @@ def main():
         out["config"].update({"mu": mu, "prandtl": prandtl})
 
     if viscous and not args.no_roofline:
-        # Three launches per stage: the inviscid rate, then the viscous flux
-        # and the viscous rate with the RK update (timed together).  Average
-        # durations from the library's HIP events on its stream.
+        # Per stage the viscous flux (with the inviscid rate, when fused) and
+        # the viscous rate with the RK update, timed together; unfused, the
+        # inviscid rate's launch before them.  Average durations from the
+        # library's HIP events on its stream.
         dg.dg_set_timing(s.ctx, True)
         s.step(Q, res, dt, nsteps=K)
         t = dg.dg_timing_read(s.ctx)
         dg.dg_set_timing(s.ctx, False)
+        fused = t["rhs"][1] == 0
+        vb = VISC_BYTES_FUSED if fused else VISC_BYTES
+        labels = {"rhs": "inviscid rate (k_stage_nb, RHS mode)",
+                  "visc": ("k_visc_flux (with the inviscid rate) + k_visc_apply" if fused
+                           else "k_visc_flux + k_visc_apply")}
         parts = {}
-        for kind, label in (("rhs", "inviscid rate (k_stage_nb, RHS mode)"),
-                            ("visc", "k_visc_flux + k_visc_apply")):
+        for kind in vb:
             k_ms, k_n = t[kind]
             a_s = k_ms / k_n * 1e-3
-            parts[kind] = {"kernel": label, "avg_launch_us": a_s * 1e6, "launches": k_n,
-                           "alg_bytes_per_launch": VISC_BYTES[kind] * dof,
-                           "achieved": VISC_BYTES[kind] * dof / a_s / 1e9}
+            parts[kind] = {"kernel": labels[kind], "avg_launch_us": a_s * 1e6, "launches": k_n,
+                           "alg_bytes_per_launch": vb[kind] * dof,
+                           "achieved": vb[kind] * dof / a_s / 1e9}
         v = parts["visc"]
         out["roofline"] = {"bound": "hbm", "achieved": v["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": v["achieved"] / HBM_PEAK_GBS,
                            "traffic": measured_traffic(args.workload, "visc", s.options()),
-                           "kernel": "k_visc_flux + k_visc_apply (viscous terms and LSERK45 update, one stage)",
+                           "kernel": (("k_visc_flux (viscous flux and inviscid rate) + k_visc_apply (viscous "
+                                       "rate and LSERK45 update), one stage") if fused else
+                                      "k_visc_flux + k_visc_apply (viscous terms and LSERK45 update, one stage)"),
                            "avg_launch_us": v["avg_launch_us"], "launches": v["launches"],
                            "alg_bytes_per_launch": v["alg_bytes_per_launch"],
-                           "inviscid_rate": parts["rhs"],
-                           "stage_bytes_per_node": sum(VISC_BYTES.values())}
+                           "stage_bytes_per_node": sum(vb.values())}
+        if not fused:
+            out["roofline"]["inviscid_rate"] = parts["rhs"]
     elif not args.no_roofline:
         # Dominant kernel: the fused stage kernel of stages 2..5 (four of the
         # five launches of a step; the first stage's kernel, which does not

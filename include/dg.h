@@ -152,16 +152,22 @@ int dg_set_volume_form(dg_ctx* ctx, int form);
  * DG_OPT_XCD_REMAP: 1 gives each of the 8 XCDs of the MI355X (each with
  *   its own L2) a contiguous part of the visiting order; 0 leaves the
  *   hardware's round-robin spread of workgroups over the XCDs.
+ * DG_OPT_VISC_FUSED: with viscosity set (FP64, standard volume form), 1
+ *   forms the inviscid rate inside the viscous-flux launch from the
+ *   neighbour loads that launch makes anyway; 0 gives it a launch of its
+ *   own (the neighbour-read kernel).  Bitwise the same results.
  * Defaults (read back with dg_get_option): DG_EXCHANGE_NEIGHBOUR,
- * DG_ORDER_PENCIL with 16 x 8 pencils and DG_OPT_XCD_REMAP 1, the fastest
- * setting measured on the Taylor-Green workloads at p = 3, 4 and 6. */
+ * DG_ORDER_PENCIL with 16 x 8 pencils, DG_OPT_XCD_REMAP 1 and
+ * DG_OPT_VISC_FUSED 1, the fastest setting measured on the Taylor-Green
+ * workloads at p = 3, 4 and 6. */
 enum {
   DG_OPT_EXCHANGE = 1,
   DG_OPT_XCD_REMAP = 2,
   DG_OPT_ORDER = 3,
   DG_OPT_PENCIL_X = 4,
   DG_OPT_PENCIL_Z = 5,
-  DG_OPT_BATCH_LAUNCH = 6   /* batched meshes only (dg_batch_set_option) */
+  DG_OPT_BATCH_LAUNCH = 6,  /* batched meshes only (dg_batch_set_option) */
+  DG_OPT_VISC_FUSED = 7
 };
 enum { DG_EXCHANGE_TRACES = 0, DG_EXCHANGE_NEIGHBOUR = 1 };
 enum { DG_ORDER_LINEAR = 0, DG_ORDER_PENCIL = 1 };

@@ -235,18 +235,30 @@ int stages_split(dg_ctx* c, double* Q, double* res, double dt, int s0, int count
   return DG_OK;
 }
 
-// Navier-Stokes stages: per stage the inviscid rate into the workspace, then
-// the viscous flux and the viscous rate, combined with the inviscid one into
-// the LSERK45 update of Q and res in place.
+// Whether the viscous-flux launch forms the inviscid rate too: the FP64
+// standard form (the split form and the FP32 form have kernels of their own).
+bool visc_fused(const dg_ctx* c) {
+  return c->visc_fused && c->volume_form == DG_VOLUME_STANDARD && c->precision == DG_FP64;
+}
+
+// Navier-Stokes stages: per stage the inviscid rate into the workspace (in
+// the viscous-flux launch, or before it), the viscous flux, and the viscous
+// rate, combined with the inviscid one into the LSERK45 update of Q and res
+// in place.
 int stages_visc(dg_ctx* c, double* Q, double* res, double dt, int s0, int count) {
   const DGWorkspace L = dg_workspace_layout(c);
   double* R = (double*)(c->ws + L.off_visc_r);
   double* Fv = (double*)(c->ws + L.off_visc_fv);
+  const bool fused = visc_fused(c);
   for (int g = 0; g < count; ++g) {
     const int s = (s0 + g) % 5;
-    int err = timed(c, TK_RHS, [&] { return euler_rate_nb(c, Q, R); });
-    if (err) return hip_fail(err, "inviscid rate launch");
-    err = timed(c, TK_VISC, [&] { return dg_launch_visc(c, Q, Fv, R, Q, res, 1, kRKA[s], kRKB[s], dt, s == 0); });
+    int err = 0;
+    if (!fused) {
+      err = timed(c, TK_RHS, [&] { return euler_rate_nb(c, Q, R); });
+      if (err) return hip_fail(err, "inviscid rate launch");
+    }
+    err = timed(c, TK_VISC,
+                [&] { return dg_launch_visc(c, Q, Fv, R, Q, res, 1, kRKA[s], kRKB[s], dt, s == 0, fused); });
     if (err) return hip_fail(err, "viscous stage launch");
   }
   return DG_OK;
@@ -461,6 +473,7 @@ dg_ctx* dg_create(int nx, int ny, int nz, int p, double gamma) {
   c->xcd_remap = 1;
   c->pencil_x = 16;
   c->pencil_z = 8;
+  c->visc_fused = 1;
   c->mu = 0.0;
   c->prandtl = 0.72;
   c->kappa = 0.0;
@@ -610,6 +623,11 @@ int dg_set_option(dg_ctx* c, int key, int value) {
     ++c->epoch;
     return DG_OK;
   }
+  if (key == DG_OPT_VISC_FUSED) {
+    c->visc_fused = value ? 1 : 0;
+    ++c->epoch;
+    return DG_OK;
+  }
   return fail(DG_EINVAL, "unknown option %d", key);
 }
 
@@ -621,6 +639,7 @@ int dg_get_option(const dg_ctx* c, int key, int* value) {
     case DG_OPT_ORDER: *value = c->order; return DG_OK;
     case DG_OPT_PENCIL_X: *value = c->pencil_x; return DG_OK;
     case DG_OPT_PENCIL_Z: *value = c->pencil_z; return DG_OK;
+    case DG_OPT_VISC_FUSED: *value = c->visc_fused; return DG_OK;
     default: return fail(DG_EINVAL, "unknown option %d", key);
   }
 }
@@ -661,11 +680,16 @@ int dg_rhs(dg_ctx* c, const double* Q, double* R) {
   if (rc) return rc;
   const bool f32 = c->precision == DG_FP32_MFMA;
   if (c->mu > 0.0 || c->volume_form == DG_VOLUME_KEP) {
-    int err = timed(c, TK_RHS, [&] { return euler_rate_nb(c, Q, R); });
-    if (err) return hip_fail(err, "rhs launch");
+    const bool fused = c->mu > 0.0 && visc_fused(c);
+    int err = 0;
+    if (!fused) {
+      err = timed(c, TK_RHS, [&] { return euler_rate_nb(c, Q, R); });
+      if (err) return hip_fail(err, "rhs launch");
+    }
     if (c->mu == 0.0) return DG_OK;
     double* Fv = (double*)(c->ws + dg_workspace_layout(c).off_visc_fv);
-    err = timed(c, TK_VISC, [&] { return dg_launch_visc(c, Q, Fv, R, nullptr, nullptr, 0, 0.0, 0.0, 0.0, 0); });
+    err = timed(c, TK_VISC,
+                [&] { return dg_launch_visc(c, Q, Fv, R, nullptr, nullptr, 0, 0.0, 0.0, 0.0, 0, fused); });
     if (err) return hip_fail(err, "viscous rate launch");
     return DG_OK;
   }

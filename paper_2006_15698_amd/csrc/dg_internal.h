@@ -52,6 +52,7 @@ struct dg_ctx {
   int order;      // DG_ORDER_LINEAR or DG_ORDER_PENCIL
   int pencil_x;   // pencil extent along x in elements (0: whole row)
   int pencil_z;   // pencil extent along z in element planes
+  int visc_fused; // viscous FP64 standard form: inviscid rate inside the viscous-flux launch
   // viscous terms (dg_set_viscosity): dynamic viscosity, Prandtl number and
   // conductivity mu gamma / ((gamma - 1) Pr); mu = 0 is the Euler equations
   double mu, prandtl, kappa;
@@ -133,11 +134,12 @@ int dg_launch_reduce(const dg_ctx* c, const double* Q, double* red);
 // Adjoint RHS.
 int dg_launch_vjp(const dg_ctx* c, const double* Q, const double* gR, double* gQ, char* scratch);
 
-// Viscous terms (kern_visc.hip): the nodal viscous flux of Q into Fv, then
-// mode 0: R += the viscous rate; mode 1: the LSERK45 stage in place on Qu
-// and res with R the inviscid rate of the stage.
+// Viscous terms (kern_visc.hip): the nodal viscous flux of Q into Fv (with
+// `rate` also the inviscid rate of the standard form into R), then mode 0:
+// R += the viscous rate; mode 1: the LSERK45 stage in place on Qu and res
+// with R the inviscid rate of the stage.
 int dg_launch_visc(const dg_ctx* c, const double* Q, double* Fv, double* R, double* Qu, double* res, int mode,
-                   double a, double b, double dt, int first);
+                   double a, double b, double dt, int first, bool rate);
 
 // Kinetic-energy-preserving split form (kern_split.hip): mode 0 RR = dQ/dt;
 // mode 1 the LSERK45 stage Qin -> Qout with res = RR in place; mode 2 the

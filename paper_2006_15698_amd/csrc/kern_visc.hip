@@ -99,12 +99,17 @@ __device__ __forceinline__ double br1_line(const DGTables& tb, const double* X, 
 
 // A neighbour's primitive trace on our face point pt of direction D: its
 // -D face (s = 1, our +D face) or its +D face (s = 0), from its state at q
-// (field stride fs), summed over its normal line.
-template <int N, int D>
+// (field stride fs), summed over its normal line; with CONS also its
+// conserved trace from the same loads (the FMA chain of line_trace).
+template <int N, int D, bool CONS>
 __device__ __forceinline__ void prim_trace(const DGTables& tb, const double* __restrict__ q, int64_t fs, int s,
-                                           int pt, double* acc) {
+                                           int pt, double* acc, double* cons) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = 0.0;
+  if (CONS) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) cons[f] = 0.0;
+  }
 #pragma unroll
   for (int m = 0; m < N; ++m) {
     const int node = dgdev::tnode<N>(D, m, pt);
@@ -115,7 +120,30 @@ __device__ __forceinline__ void prim_trace(const DGTables& tb, const double* __r
     const double wgt = s ? tb.lm[m] : tb.lp[m];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = fma(wgt, p[c], acc[c]);
+    if (CONS) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) cons[f] = fma(wgt, v[f], cons[f]);
+    }
   }
+}
+
+// Local Lax-Friedrichs flux at face point pt of face 2D + s from the
+// element's own trace (interpolated from its state S in LDS) and the
+// neighbour's (in H, overwritten with the flux).
+template <int N, int D>
+__device__ __forceinline__ void face_flux(const DGTables& tb, const double (*S)[VCfg<N>::N3],
+                                          double (*H)[VCfg<N>::N2], int s, int pt) {
+  double own[5], qm[5], qp[5], fl[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    own[f] = dgdev::line_trace<N>(S[f], s ? tb.lp : tb.lm, D, pt);
+    const double nb = H[f][pt];
+    qm[f] = s ? own[f] : nb;
+    qp[f] = s ? nb : own[f];
+  }
+  dgdev::lf_flux_d<D>(qm, qp, tb.gamma, tb.gm1, fl);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) H[f][pt] = fl[f];
 }
 
 // A neighbour's trace of its direction-D viscous flux (4 values) on our
@@ -134,25 +162,39 @@ __device__ __forceinline__ void flux_trace(const DGTables& tb, const double* __r
   }
 }
 
-template <int N>
+// RATE: the inviscid (Euler) rate of the standard form as well, into R: the
+// neighbours' conserved traces come from the loads of their primitive
+// traces, the element's own from its state in LDS; the operations and their
+// order are those of the fused Euler stage (same traces, Lax-Friedrichs
+// flux, pointwise flux staged per direction, contraction and lift), so R
+// equals the neighbour-read kernel's rate.
+template <int N, bool RATE>
 __global__ void __launch_bounds__(VCfg<N>::NT)
-k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, double mu, double kappa,
-            DGOrder ord) {
+k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, double* __restrict__ R, double mu,
+            double kappa, DGOrder ord) {
   constexpr int N2 = VCfg<N>::N2, N3 = VCfg<N>::N3, NT = VCfg<N>::NT;
+  constexpr int RN3 = RATE ? N3 : 1, RN2 = RATE ? N2 : 1;
   __shared__ double P[4][N3];
   __shared__ double Tn[6][4][N2];   // face 2d + s: neighbour's trace (s = 0: -d face, 1: +d face)
+  __shared__ double S[5][RN3];      // RATE: the state, then one direction's pointwise Euler flux
+  __shared__ double H[6][5][RN2];   // RATE: the neighbour's conserved trace, then the face flux
   // the element of this workgroup in the visiting order (pencils, XCD chunks)
   int e, ne;
   dgdev::block_elements<1>(tb, ord, blockIdx.x, gridDim.x, e, ne);
   const int t = threadIdx.x;
   const int64_t fs = (int64_t)tb.E * N3;
+  double q[5];
   if (t < N3) {
-    double q[5], p[4];
+    double p[4];
 #pragma unroll
     for (int f = 0; f < 5; ++f) q[f] = Q[f * fs + (int64_t)e * N3 + t];
     primitive(q, tb.gm1, p);
 #pragma unroll
     for (int c = 0; c < 4; ++c) P[c][t] = p[c];
+    if (RATE) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) S[f][RATE ? t : 0] = q[f];
+    }
   }
   const int wave = t >> 6, lane = t & 63;
   for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
@@ -160,41 +202,104 @@ k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, 
     if (face_lane<N>(sl, lane, face, pt)) {
       const int s = face & 1;
       const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, face >> 1, s ? 1 : -1);
-      double acc[4];
+      double acc[4], cons[5];
       switch (face >> 1) {   // uniform over the wave
-        case 0: prim_trace<N, 0>(tb, Q + (int64_t)en * N3, fs, s, pt, acc); break;
-        case 1: prim_trace<N, 1>(tb, Q + (int64_t)en * N3, fs, s, pt, acc); break;
-        default: prim_trace<N, 2>(tb, Q + (int64_t)en * N3, fs, s, pt, acc); break;
+        case 0: prim_trace<N, 0, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
+        case 1: prim_trace<N, 1, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
+        default: prim_trace<N, 2, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
+      if (RATE) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) H[face][f][RATE ? pt : 0] = cons[f];
+      }
     }
   }
   __syncthreads();
-  if (t >= N3) return;
-  const int i = t % N, j = (t / N) % N, k = t / N2;
-  double th[3][4];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int m0, pt;
-    line_of<N>(d, i, j, k, m0, pt);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) th[d][c] = br1_line<N>(tb, P[c], d, m0, pt, Tn[2 * d][c][pt], Tn[2 * d + 1][c][pt]);
-  }
-  const double u[3] = {P[0][t], P[1][t], P[2][t]};
-  const double div = th[0][0] + th[1][1] + th[2][2];
-  const int64_t g = (int64_t)e * N3 + t;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double en = kappa * th[d][3];
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk) {
-      double tau = mu * (th[d][kk] + th[kk][d]);
-      if (kk == d) tau = tau - (2.0 / 3.0) * mu * div;
-      Fv[(d * 4 + kk) * fs + g] = tau;
-      en = en + u[kk] * tau;
+  if constexpr (RATE) {
+    // the face fluxes (each lane rewrites only its own points of H)
+    for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
+      int face, pt;
+      if (face_lane<N>(sl, lane, face, pt)) {
+        switch (face >> 1) {
+          case 0: face_flux<N, 0>(tb, S, H[face], face & 1, pt); break;
+          case 1: face_flux<N, 1>(tb, S, H[face], face & 1, pt); break;
+          default: face_flux<N, 2>(tb, S, H[face], face & 1, pt); break;
+        }
+      }
     }
-    Fv[(d * 4 + 3) * fs + g] = en;
+  } else if (t >= N3) {
+    return;
+  }
+  const bool node = t < N3;
+  const int i = t % N, j = (t / N) % N, k = t / N2;
+  const int64_t g = (int64_t)e * N3 + t;
+  if (node) {
+    double th[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int m0, pt;
+      line_of<N>(d, i, j, k, m0, pt);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) th[d][c] = br1_line<N>(tb, P[c], d, m0, pt, Tn[2 * d][c][pt], Tn[2 * d + 1][c][pt]);
+    }
+    const double u[3] = {P[0][t], P[1][t], P[2][t]};
+    const double div = th[0][0] + th[1][1] + th[2][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double en = kappa * th[d][3];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        double tau = mu * (th[d][kk] + th[kk][d]);
+        if (kk == d) tau = tau - (2.0 / 3.0) * mu * div;
+        Fv[(d * 4 + kk) * fs + g] = tau;
+        en = en + u[kk] * tau;
+      }
+      Fv[(d * 4 + 3) * fs + g] = en;
+    }
+  }
+  if (!RATE) return;
+  // Euler volume term: per direction the pointwise flux into S (free once
+  // every face flux is formed), then the contraction along the node's line
+  // and the lift of the two face fluxes on it
+  double rinv = 0.0, pr = 0.0;
+  if (node) {
+    rinv = dgdev::recip(q[0]);
+    pr = tb.gm1 * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * rinv);
+  }
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();   // S (state, or the previous direction's flux) is no longer read
+    if (node) {
+      const double ud = q[1 + d] * rinv;
+      S[0][RATE ? t : 0] = q[1 + d];
+      S[1][RATE ? t : 0] = q[1] * ud + (d == 0 ? pr : 0.0);
+      S[2][RATE ? t : 0] = q[2] * ud + (d == 1 ? pr : 0.0);
+      S[3][RATE ? t : 0] = q[3] * ud + (d == 2 ? pr : 0.0);
+      S[4][RATE ? t : 0] = (q[4] + pr) * ud;
+    }
+    __syncthreads();
+    if (node) {
+      int m, pt;
+      line_of<N>(d, i, j, k, m, pt);
+      const double sc = tb.sc[d];
+      const double lfm = tb.liftm[m], lfp = tb.liftp[m];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        double sm = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) sm = fma(tb.Dh[m * N + a], S[f][RATE ? dgdev::tnode<N>(d, a, pt) : 0], sm);
+        sm = fma(lfm, H[2 * d][f][RATE ? pt : 0], sm);
+        sm = fma(-lfp, H[2 * d + 1][f][RATE ? pt : 0], sm);
+        acc[f] = fma(sc, sm, acc[f]);
+      }
+    }
+  }
+  if (node) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) R[f * fs + g] = acc[f];
   }
 }
 
@@ -264,11 +369,15 @@ k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R,
 
 template <int N>
 int launch_visc_n(const dg_ctx* c, const double* Q, double* Fv, double* R, double* Qu, double* res, int mode,
-                  double a, double b, double dt, int first) {
+                  double a, double b, double dt, int first, bool rate) {
   unsigned grid;
   const DGOrder ord = dg_order(c, 1, &grid);
   const dim3 blk(VCfg<N>::NT);
-  hipLaunchKernelGGL(k_visc_flux<N>, dim3(grid), blk, 0, c->stream, c->tab, Q, Fv, c->mu, c->kappa, ord);
+  if (rate)
+    hipLaunchKernelGGL((k_visc_flux<N, true>), dim3(grid), blk, 0, c->stream, c->tab, Q, Fv, R, c->mu, c->kappa, ord);
+  else
+    hipLaunchKernelGGL((k_visc_flux<N, false>), dim3(grid), blk, 0, c->stream, c->tab, Q, Fv, nullptr, c->mu,
+                       c->kappa, ord);
   if (mode == 0)
     hipLaunchKernelGGL((k_visc_apply<N, 0>), dim3(grid), blk, 0, c->stream, c->tab, Fv, R, nullptr, nullptr, a, b,
                        dt, ord);
@@ -282,16 +391,16 @@ int launch_visc_n(const dg_ctx* c, const double* Q, double* Fv, double* R, doubl
 }  // namespace
 
 int dg_launch_visc(const dg_ctx* c, const double* Q, double* Fv, double* R, double* Qu, double* res, int mode,
-                   double a, double b, double dt, int first) {
+                   double a, double b, double dt, int first, bool rate) {
   switch (c->N) {
-    case 1: return launch_visc_n<1>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
-    case 2: return launch_visc_n<2>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
-    case 3: return launch_visc_n<3>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
-    case 4: return launch_visc_n<4>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
-    case 5: return launch_visc_n<5>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
-    case 6: return launch_visc_n<6>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
-    case 7: return launch_visc_n<7>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
-    case 8: return launch_visc_n<8>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first);
+    case 1: return launch_visc_n<1>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first, rate);
+    case 2: return launch_visc_n<2>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first, rate);
+    case 3: return launch_visc_n<3>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first, rate);
+    case 4: return launch_visc_n<4>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first, rate);
+    case 5: return launch_visc_n<5>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first, rate);
+    case 6: return launch_visc_n<6>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first, rate);
+    case 7: return launch_visc_n<7>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first, rate);
+    case 8: return launch_visc_n<8>(c, Q, Fv, R, Qu, res, mode, a, b, dt, first, rate);
     default: return (int)hipErrorInvalidValue;
   }
 }

@@ -48,10 +48,11 @@ DG_EXCHANGE_NEIGHBOUR = 1
 DG_ORDER_LINEAR = 0
 DG_ORDER_PENCIL = 1
 DG_OPT_BATCH_LAUNCH = 6
+DG_OPT_VISC_FUSED = 7
 DG_BATCH_PERSISTENT = 0
 DG_BATCH_PER_DEGREE = 1
 OPTION_NAMES = {DG_OPT_EXCHANGE: "exchange", DG_OPT_XCD_REMAP: "xcd_remap", DG_OPT_ORDER: "order",
-                DG_OPT_PENCIL_X: "pencil_x", DG_OPT_PENCIL_Z: "pencil_z"}
+                DG_OPT_PENCIL_X: "pencil_x", DG_OPT_PENCIL_Z: "pencil_z", DG_OPT_VISC_FUSED: "visc_fused"}
 BATCH_OPTION_NAMES = {DG_OPT_XCD_REMAP: "xcd_remap", DG_OPT_ORDER: "order", DG_OPT_PENCIL_X: "pencil_x",
                       DG_OPT_PENCIL_Z: "pencil_z", DG_OPT_BATCH_LAUNCH: "batch_launch"}
 

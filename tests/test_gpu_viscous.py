@@ -2,6 +2,7 @@
 ``NavierStokesDG``: the right-hand side element by element for p = 0..7 on
 ragged anisotropic meshes, LSERK45 steps, the Taylor-Green vortex at
 Re = 1600 on the 48^3 p=4 mesh on sampled elements (5x5x5 periodic patches),
+the inviscid rate formed in the viscous-flux launch against its own launch,
 conservation over steps, and the calls that the viscous terms do not cover."""
 
 import ctypes
@@ -91,6 +92,30 @@ def test_viscous_steps_vs_oracle(dgm, p):
     s.step(Qb, rb, dt, nsteps=3, graph=True)
     torch.cuda.synchronize()
     assert torch.equal(Qb, Q)
+
+
+@pytest.mark.parametrize("p,n", [(0, (3, 2, 4)), (1, (4, 3, 2)), (2, (3, 4, 2)), (3, (3, 4, 5)), (4, (4, 3, 3)),
+                                 (5, (3, 2, 3)), (6, (2, 3, 2)), (7, (2, 2, 3))])
+def test_fused_inviscid_rate_equals_its_own_launch(dgm, p, n):
+    """The inviscid rate formed inside the viscous-flux launch against the
+    neighbour-read kernel's launch of its own: the same bits, for the
+    right-hand side and over steps."""
+    import torch
+    L = (1.0, 1.2, 0.8)
+    print(f"[visc fused p={p} n={n}]", flush=True)
+    Q0 = W.random_smooth(n, p, seed=260 + p, L=L, noise=0.03)
+    fused = dgm.Solver(n, p, L=L, mu=0.03, prandtl=0.7)
+    split = dgm.Solver(n, p, L=L, mu=0.03, prandtl=0.7)
+    split.set_option(dgm.DG_OPT_VISC_FUSED, 0)
+    assert fused.options()["visc_fused"] == 1 and split.options()["visc_fused"] == 0
+    Q = _dev(Q0)
+    assert torch.equal(fused.rhs(Q), split.rhs(Q))
+    Qa, Qb = _dev(Q0), _dev(Q0)
+    ra, rb = torch.zeros_like(Qa), torch.zeros_like(Qb)
+    fused.step(Qa, ra, 1e-4, nsteps=2)
+    split.step(Qb, rb, 1e-4, nsteps=2)
+    torch.cuda.synchronize()
+    assert torch.equal(Qa, Qb) and torch.equal(ra, rb)
 
 
 def test_viscous_conservation_over_steps(dgm):
