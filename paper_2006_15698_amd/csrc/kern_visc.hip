@@ -50,6 +50,20 @@ struct VCfg {
   static constexpr int NSLOT = 6 / FPW;
 };
 
+// The flux launch's neighbour-trace phase: WX wave-sized slots for the x-face
+// points (one per lane), then slots for the y/z-face point pairs (NYZ pairs,
+// H per row).
+template <int N>
+struct PairCfg {
+  // a pair needs rows of two points; at N = 7, 8 the pair slots would
+  // leave waves of the workgroup idle in this phase (p = 6: 2.6% slower)
+  static constexpr bool PAIRS = N >= 2 && N <= 6;
+  static constexpr int H = (N + 1) / 2;
+  static constexpr int NYZ = 4 * N * H;
+  static constexpr int WX = (2 * N * N + 63) / 64;
+  static constexpr int SLOTS = WX + (NYZ + 63) / 64;
+};
+
 // Face and tangential point of lane `lane` in face slot `s`; false for the
 // lanes past the face's points.
 template <int N>
@@ -127,6 +141,47 @@ __device__ __forceinline__ void prim_trace(const DGTables& tb, const double* __r
   }
 }
 
+// prim_trace for the two points a0, a0 + 1 of row b of a y- or z-face
+// (tangential index a + N b): their normal-line nodes a + m sm + b sb
+// (sm, sb = N, N^2 for y and N^2, N for z) are next to each other in memory
+// at every position m, so one 16-byte load (a multi-dword access needs only
+// dword alignment) brings a field's value for both.  Per point the FMA
+// chains of prim_trace.
+template <int N, bool CONS>
+__device__ __forceinline__ void prim_trace_pair(const DGTables& tb, const double* __restrict__ q, int64_t fs, int s,
+                                                int sm, int node0, double (*acc)[4], double (*cons)[5]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[h][c] = 0.0;
+    if (CONS) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) cons[h][f] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int node = node0 + m * sm;
+    double2 w[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) __builtin_memcpy(&w[f], q + f * fs + node, 16);
+    const double wgt = s ? tb.lm[m] : tb.lp[m];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double v[5], p[4];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) v[f] = h ? w[f].y : w[f].x;
+      primitive(v, tb.gm1, p);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[h][c] = fma(wgt, p[c], acc[h][c]);
+      if (CONS) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) cons[h][f] = fma(wgt, v[f], cons[h][f]);
+      }
+    }
+  }
+}
+
 // Local Lax-Friedrichs flux at face point pt of face 2D + s from the
 // element's own trace (interpolated from its state S in LDS) and the
 // neighbour's (in H, overwritten with the flux).
@@ -197,22 +252,67 @@ k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, 
     }
   }
   const int wave = t >> 6, lane = t & 63;
-  for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
-    int face, pt;
-    if (face_lane<N>(sl, lane, face, pt)) {
-      const int s = face & 1;
-      const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, face >> 1, s ? 1 : -1);
-      double acc[4], cons[5];
-      switch (face >> 1) {   // uniform over the wave
-        case 0: prim_trace<N, 0, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
-        case 1: prim_trace<N, 1, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
-        default: prim_trace<N, 2, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
+  using PC = PairCfg<N>;
+  if constexpr (!PC::PAIRS) {
+    for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
+      int face, pt;
+      if (face_lane<N>(sl, lane, face, pt)) {
+        const int s = face & 1;
+        const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, face >> 1, s ? 1 : -1);
+        double acc[4], cons[5];
+        switch (face >> 1) {   // uniform over the wave
+          case 0: prim_trace<N, 0, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
+          case 1: prim_trace<N, 1, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
+          default: prim_trace<N, 2, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons); break;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
+        if (RATE) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) H[face][f][RATE ? pt : 0] = cons[f];
+        }
       }
+    }
+  } else for (int sl = wave; sl < PC::SLOTS; sl += VCfg<N>::NW) {
+    if (sl < PC::WX) {
+      // x-faces: one point per lane
+      const int it = sl * 64 + lane;
+      if (it < 2 * N2) {
+        const int s = it >= N2, pt = it - s * N2, face = s;
+        const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, 0, s ? 1 : -1);
+        double acc[4], cons[5];
+        prim_trace<N, 0, RATE>(tb, Q + (int64_t)en * N3, fs, s, pt, acc, cons);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
-      if (RATE) {
+        for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
+        if (RATE) {
 #pragma unroll
-        for (int f = 0; f < 5; ++f) H[face][f][RATE ? pt : 0] = cons[f];
+          for (int f = 0; f < 5; ++f) H[face][f][RATE ? pt : 0] = cons[f];
+        }
+      }
+    } else {
+      // y- and z-faces: two points of a row per lane (rows of odd length
+      // end in a pair that overlaps the one before it; both write the same
+      // values for the shared point)
+      const int it = (sl - PC::WX) * 64 + lane;
+      if (it < PC::NYZ) {
+        const int qf = it / (N * PC::H), r = it - qf * (N * PC::H);
+        const int b = r / PC::H, c2 = r - b * PC::H;
+        const int a0 = 2 * c2 < N - 2 ? 2 * c2 : N - 2;
+        const int d = 1 + (qf >> 1), s = qf & 1, face = 2 * d + s;
+        const int sm = d == 1 ? N : N2, sb = d == 1 ? N2 : N;
+        const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
+        double acc[2][4], cons[2][5];
+        prim_trace_pair<N, RATE>(tb, Q + (int64_t)en * N3, fs, s, sm, a0 + b * sb, acc, cons);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int pt = a0 + h + N * b;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[h][c];
+          if (RATE) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) H[face][f][RATE ? pt : 0] = cons[h][f];
+          }
+        }
       }
     }
   }
