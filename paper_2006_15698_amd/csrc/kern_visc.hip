@@ -217,6 +217,30 @@ __device__ __forceinline__ void flux_trace(const DGTables& tb, const double* __r
   }
 }
 
+// flux_trace for a pair of points of a y- or z-face (direction d), as
+// prim_trace_pair.
+template <int N>
+__device__ __forceinline__ void flux_trace_pair(const DGTables& tb, const double* __restrict__ fv, int64_t fs, int s,
+                                                int d, int sm, int node0, double (*acc)[4]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[h][c] = 0.0;
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int node = node0 + m * sm;
+    const double wgt = s ? tb.lm[m] : tb.lp[m];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double2 w;
+      __builtin_memcpy(&w, fv + (d * 4 + c) * fs + node, 16);
+      acc[0][c] = fma(wgt, w.x, acc[0][c]);
+      acc[1][c] = fma(wgt, w.y, acc[1][c]);
+    }
+  }
+}
+
 // RATE: the inviscid (Euler) rate of the standard form as well, into R: the
 // neighbours' conserved traces come from the loads of their primitive
 // traces, the element's own from its state in LDS; the operations and their
@@ -425,19 +449,53 @@ k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R,
     for (int c = 0; c < 12; ++c) F[c][t] = Fv[c * fs + (int64_t)e * N3 + t];
   }
   const int wave = t >> 6, lane = t & 63;
-  for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
-    int face, pt;
-    if (face_lane<N>(sl, lane, face, pt)) {
-      const int s = face & 1;
-      const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, face >> 1, s ? 1 : -1);
-      double acc[4];
-      switch (face >> 1) {   // uniform over the wave
-        case 0: flux_trace<N, 0>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
-        case 1: flux_trace<N, 1>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
-        default: flux_trace<N, 2>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
-      }
+  using PC = PairCfg<N>;
+  if constexpr (!PC::PAIRS) {
+    for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
+      int face, pt;
+      if (face_lane<N>(sl, lane, face, pt)) {
+        const int s = face & 1;
+        const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, face >> 1, s ? 1 : -1);
+        double acc[4];
+        switch (face >> 1) {   // uniform over the wave
+          case 0: flux_trace<N, 0>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
+          case 1: flux_trace<N, 1>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
+          default: flux_trace<N, 2>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc); break;
+        }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
+        for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
+      }
+    }
+  } else for (int sl = wave; sl < PC::SLOTS; sl += VCfg<N>::NW) {
+    if (sl < PC::WX) {
+      // x-faces: one point per lane
+      const int it = sl * 64 + lane;
+      if (it < 2 * N2) {
+        const int s = it >= N2, pt = it - s * N2, face = s;
+        const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, 0, s ? 1 : -1);
+        double acc[4];
+        flux_trace<N, 0>(tb, Fv + (int64_t)en * N3, fs, s, pt, acc);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Tn[face][c][pt] = acc[c];
+      }
+    } else {
+      // y- and z-faces: two points of a row per lane, as in the flux launch
+      const int it = (sl - PC::WX) * 64 + lane;
+      if (it < PC::NYZ) {
+        const int qf = it / (N * PC::H), r = it - qf * (N * PC::H);
+        const int b = r / PC::H, c2 = r - b * PC::H;
+        const int a0 = 2 * c2 < N - 2 ? 2 * c2 : N - 2;
+        const int d = 1 + (qf >> 1), s = qf & 1, face = 2 * d + s;
+        const int sm = d == 1 ? N : N2, sb = d == 1 ? N2 : N;
+        const int en = dgdev::neighbour(tb.nx, tb.ny, tb.nz, e, d, s ? 1 : -1);
+        double acc[2][4];
+        flux_trace_pair<N>(tb, Fv + (int64_t)en * N3, fs, s, d, sm, a0 + b * sb, acc);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Tn[face][c][a0 + h + N * b] = acc[h][c];
+        }
+      }
     }
   }
   __syncthreads();
