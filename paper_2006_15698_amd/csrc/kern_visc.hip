@@ -22,12 +22,14 @@
 // contiguous part), one thread per node:
 //   k_visc_flux  Q -> F_v at every node (12 values: 4 per direction);
 //                the neighbours' primitive traces are interpolated from
-//                their state in the same launch;
-//   k_visc_apply F_v -> the viscous rate, added to the inviscid rate R that
-//                the inviscid stage kernel wrote (MODE 0), or combined with
-//                it into the LSERK45 update of Q and res in place (MODE 1,
-//                MODE 2 for the first stage: no launch reads another
-//                element's Q here).
+//                their state in the same launch (on y/z-faces two points per
+//                16-byte load); with RATE it writes the inviscid rate R of
+//                the standard form too, from the same neighbour loads;
+//   k_visc_apply F_v -> the viscous rate, added to the inviscid rate R (of
+//                the flux launch, or of the split-form or FP32 kernel)
+//                (MODE 0), or combined with it into the LSERK45 update of Q
+//                and res in place (MODE 1, MODE 2 for the first stage: no
+//                launch reads another element's Q here).
 
 #include "dg_internal.h"
 #include "stage_fp64.h"
