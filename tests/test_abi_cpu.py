@@ -133,6 +133,12 @@ def test_options_validate_and_read_back(dg):
         assert dg.dg_get_option(ctx, dg.DG_OPT_XCD_REMAP) == 1
         dg.dg_set_option(ctx, dg.DG_OPT_XCD_REMAP, 0)
         assert dg.dg_get_option(ctx, dg.DG_OPT_XCD_REMAP) == 0
+        # the viscous stage forms the inviscid rate in its flux launch by default
+        assert defaults[dg.DG_OPT_VISC_FUSED] == 1
+        dg.dg_set_option(ctx, dg.DG_OPT_VISC_FUSED, 0)
+        assert dg.dg_get_option(ctx, dg.DG_OPT_VISC_FUSED) == 0
+        dg.dg_set_option(ctx, dg.DG_OPT_VISC_FUSED, 3)
+        assert dg.dg_get_option(ctx, dg.DG_OPT_VISC_FUSED) == 1
         with pytest.raises(dg.DGError):
             dg.dg_set_option(ctx, 99, 0)
         with pytest.raises(dg.DGError):
