@@ -264,8 +264,31 @@ k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, 
   dgdev::block_elements<1>(tb, ord, blockIdx.x, gridDim.x, e, ne);
   const int t = threadIdx.x;
   const int64_t fs = (int64_t)tb.E * N3;
-  double q[5];
-  if (t < N3) {
+  double q[5];   // with RATE: the node's state, read back from S after the first barrier
+  if constexpr (N3 >= 2) {
+    // two nodes per lane and 16-byte load (dword alignment suffices; at odd
+    // N^3 the last pair overlaps the one before it)
+    constexpr int NP = (N3 + 1) / 2;
+    if (t < NP) {
+      const int n0 = 2 * t < N3 - 2 ? 2 * t : N3 - 2;
+      double2 w[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) __builtin_memcpy(&w[f], Q + f * fs + (int64_t)e * N3 + n0, 16);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double v[5], p[4];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) v[f] = h ? w[f].y : w[f].x;
+        primitive(v, tb.gm1, p);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) P[c][n0 + h] = p[c];
+        if (RATE) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) S[f][RATE ? n0 + h : 0] = v[f];
+        }
+      }
+    }
+  } else if (t < N3) {
     double p[4];
 #pragma unroll
     for (int f = 0; f < 5; ++f) q[f] = Q[f * fs + (int64_t)e * N3 + t];
@@ -344,6 +367,10 @@ k_visc_flux(DGTables tb, const double* __restrict__ Q, double* __restrict__ Fv, 
   }
   __syncthreads();
   if constexpr (RATE) {
+    if (N3 >= 2 && t < N3) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) q[f] = S[f][t];
+    }
     // the face fluxes (each lane rewrites only its own points of H)
     for (int sl = wave; sl < VCfg<N>::NSLOT; sl += VCfg<N>::NW) {
       int face, pt;
@@ -446,7 +473,21 @@ k_visc_apply(DGTables tb, const double* __restrict__ Fv, double* __restrict__ R,
   dgdev::block_elements<1>(tb, ord, blockIdx.x, gridDim.x, e, ne);
   const int t = threadIdx.x;
   const int64_t fs = (int64_t)tb.E * N3;
-  if (t < N3) {
+  if constexpr (N3 >= 2) {
+    // two nodes per lane and 16-byte load (dword alignment suffices; at odd
+    // N^3 the last pair overlaps the one before it)
+    constexpr int NP = (N3 + 1) / 2;
+    if (t < NP) {
+      const int n0 = 2 * t < N3 - 2 ? 2 * t : N3 - 2;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        double2 w;
+        __builtin_memcpy(&w, Fv + c * fs + (int64_t)e * N3 + n0, 16);
+        F[c][n0] = w.x;
+        F[c][n0 + 1] = w.y;
+      }
+    }
+  } else if (t < N3) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) F[c][t] = Fv[c * fs + (int64_t)e * N3 + t];
   }
